@@ -1,0 +1,151 @@
+/*
+ * adc.h -- C ABI of the MI355X library for spin-adapted, density-fitted
+ * EA/IP-ADC(n), n = 2 or 3 (closed-shell reference).
+ *
+ * The library computes the lowest charged excitations of a closed-shell
+ * system from its orbital energies and density-fitting factors:
+ *   * electron attachment (EA): matrix M+ of Eq. 7, eigenvalues
+ *     omega = E(N+1) - E(N) (the vertical attachment energy is -omega);
+ *   * ionisation (IP): the negative of M- of Eq. 9, eigenvalues
+ *     omega = E(N-1) - E(N) > 0 (ionisation energies);
+ * by the five steps of Sec. III.A: integrals from B (Eq. 38), amplitudes
+ * (Eqs. 13-14), the 1p-1p / 1h-1h block, the sigma = M Y product with an
+ * iterative (Davidson) eigensolver, and spectroscopic factors (Eqs. 16-17,
+ * 46-50).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Sizes: O = nocc, V = nvir, N = O + V, Q = naux.
+ * Orbital energies eps[N]: occupied first; Fock matrix = diag(eps).
+ * DF factors B[Q][N][N], row-major, symmetric in the last two indices:
+ *   (pq|rs) = sum_Q B[Q][p][q] B[Q][r][s]                       (Eq. 38)
+ * Vectors live in the orthonormal spin-adapted basis Z = S^{1/2} Y, where Y
+ * are the spin-adapted amplitudes of Eqs. 36-37 (and their EA analogue) and
+ * S = 1 (+) (2 - P_swap) is the metric behind the norm of Eq. 48
+ * (symmetric square root; P_swap exchanges the two like indices).  In this
+ * basis M is symmetric and a unit vector gives the renormalised amplitudes
+ * of Eqs. 46-48.  A vector of length dim is laid out as
+ *   EA: dim = V + O*V*V:  Z1[a] (V entries), then Z2[i][a][b], where a is
+ *       the attached alpha electron and (b, i) a spin-conserving pair;
+ *   IP: dim = O + V*O*O:  Z1[i] (O entries), then Z2[a][i][j], where i is
+ *       the removed alpha electron and (j, a) a spin-conserving pair.
+ * Blocks of vectors are row-major [nvec][dim].
+ *
+ * Memory and streams: pointers documented as "device" are HIP device
+ * pointers on the current device (for example torch tensors' data_ptr());
+ * "host" pointers are ordinary host memory.  All caller arrays stay owned by
+ * the caller; the library never frees them.  adc_setup copies what it needs,
+ * so eps and B may be freed after it returns.  Everything the library
+ * allocates is released by adc_destroy.  A context is bound to one HIP
+ * stream (the null stream unless adc_set_stream is called); calls on one
+ * context must not overlap.
+ *
+ * Errors: every int-returning call returns ADC_OK (0) on success, a negative
+ * ADC_E_* code on failure, or ADC_E_NOCONV (1) when a solve ran out of
+ * iterations (its outputs then hold the best current estimates).  Arguments
+ * are validated on the host before any device work; a message describing
+ * the last failure is available from adc_last_error (per context) or
+ * adc_last_error(NULL) (failures before a context exists).  No C++
+ * exception crosses this interface.
+ */
+#ifndef ADC_H
+#define ADC_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct adc_ctx adc_ctx;
+
+enum { ADC_IP = 0, ADC_EA = 1 };
+
+enum {
+    ADC_OK = 0,
+    ADC_E_ARG = -1,      /* invalid argument (checked on the host)           */
+    ADC_E_OOM = -2,      /* device allocation failed or workspace limit hit  */
+    ADC_E_HIP = -3,      /* HIP / rocBLAS runtime error                      */
+    ADC_E_STATE = -4,    /* call not valid in the context's current state    */
+    ADC_E_NUMERIC = -5,  /* non-finite values met (residual or sigma)        */
+    ADC_E_NOCONV = 1     /* solver stopped at max_iter; outputs are estimates */
+};
+
+/* Steps 1-3 of Sec. III.A.  Stages eps (device, [N]) and B (device,
+ * [Q][N][N]) into the library's layouts, computes the MP amplitudes
+ * (t2 first order; for order 3 also the second-order singles and doubles
+ * and third-order singles, Eqs. 13-14) and the 1p-1p (EA) or 1h-1h (IP)
+ * block through order `order`, and keeps everything resident on the device.
+ * Setup always runs in FP64 (the amplitudes define M).
+ * order: 2 or 3.  kind: ADC_IP or ADC_EA.  On success *out receives a new
+ * context.  Errors: ADC_E_ARG (nocc < 1, nvir < 1, naux < 1, bad order or
+ * kind, NULL pointer), ADC_E_OOM, ADC_E_HIP. */
+int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
+              int order, int kind, adc_ctx** out);
+
+/* Options (numeric values):
+ *   "precision"   0 = FP64 sigma (default), 1 = mixed: sigma contractions in
+ *                 reduced precision with FP32 accumulation, FP64 subspace,
+ *                 then FP64 refinement iterations
+ *   "block"       trial vectors per sigma launch in adc_davidson (default:
+ *                 max(nroots, 8))
+ *   "max_space"   Davidson subspace limit (default 8 * block)
+ *   "max_iter"    Davidson iteration limit (default 300)
+ *   "tol_e"       eigenvalue change tolerance in Eh (default 1e-8)
+ *   "tol_r"       residual norm tolerance (default sqrt(tol_e))
+ *   "verbose"     0/1: per-iteration line on stderr
+ * Errors: ADC_E_ARG for an unknown key or out-of-range value. */
+int adc_set_option(adc_ctx* ctx, const char* key, double value);
+
+/* Bind later calls of this context to a HIP stream (hipStream_t). */
+int adc_set_stream(adc_ctx* ctx, void* hip_stream);
+
+/* Dimension of the ADC matrix (see the layout above); -1 for NULL. */
+long long adc_dim(const adc_ctx* ctx);
+
+/* Exact diagonal of M in the Z basis.  d: device [dim] (written). */
+int adc_diag(adc_ctx* ctx, double* d);
+
+/* sigma = M X for a block of vectors (step 4, Eqs. 36-37 and their EA
+ * analogue).  X: device [nvec][dim] (read), Y: device [nvec][dim] (written);
+ * X and Y must not overlap.  Runs in the precision selected by
+ * "precision" (FP64 by default).  nvec >= 1. */
+int adc_sigma(adc_ctx* ctx, const double* X, double* Y, int nvec);
+
+/* Lowest `nroots` eigenpairs by block Davidson-Liu in an FP64 subspace
+ * (steps 4-5): initial guesses are unit vectors at the smallest diagonal
+ * entries unless adc_set_guess provided vectors; the diagonal
+ * preconditioner (theta - D)^-1 corrects the residuals.  Converged when
+ * every root changes by <= tol_e and has residual norm <= tol_r.
+ * energies, spec_factors: host [nroots] (written; spec_factors may be NULL);
+ * P = 2 sum_p |X_p|^2 (Eq. 50, the sum over both spin components).
+ * vecs: device [nroots][dim] (written) or NULL.  n_iter: host, may be NULL.
+ * Returns ADC_OK, ADC_E_NOCONV (estimates written), or an error. */
+int adc_davidson(adc_ctx* ctx, int nroots, double* energies, double* spec_factors,
+                 double* vecs, int* n_iter);
+
+/* Spectroscopic factors P = 2 sum_p X_p^2 with X = T Y (Eqs. 16, 46-50)
+ * for normalised Z-basis vectors.  vecs: device [nvec][dim];
+ * P: host [nvec].  X (optional, device [nvec][N], may be NULL) receives
+ * the spectroscopic amplitudes X_p (occupied orbitals first). */
+int adc_spec_factors(adc_ctx* ctx, const double* vecs, int nvec, double* P, double* X);
+
+/* Warm start: the next adc_davidson starts from these nvec vectors
+ * (device [nvec][dim], copied). */
+int adc_set_guess(adc_ctx* ctx, const double* V0, int nvec);
+
+/* Message describing the last failure of ctx (or of a call that had no
+ * context when ctx is NULL).  Never NULL; owned by the library. */
+const char* adc_last_error(const adc_ctx* ctx);
+
+/* Release everything the context owns.  NULL is ignored. */
+void adc_destroy(adc_ctx* ctx);
+
+/* Statistics of the last adc_davidson call: iterations, sigma calls
+ * (vectors), mixed-precision iterations, wall seconds.  host arrays. */
+int adc_last_stats(const adc_ctx* ctx, int* iters, long long* sigma_vectors,
+                   int* mixed_iters, double* seconds);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADC_H */

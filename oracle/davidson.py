@@ -88,6 +88,8 @@ def davidson(sigma, diag, nroots, block=None, tol_e=1e-8, tol_r=None,
             if nrm > 1e-10:
                 new.append(d / nrm)
         if not new:
+            # the space is invariant to working precision
+            converged = bool(np.all(rnorm[:nroots] <= tol_r))
             break
         Nw = np.array(new)
         V = np.vstack([V, Nw])

@@ -1,0 +1,174 @@
+"""Python binding of the MI355X EA/IP-ADC(n) library (libadc.so).
+
+Argument marshalling only: every step runs in the HIP library.  Device
+arrays are torch CUDA (HIP) tensors; PyTorch provides memory and streams.
+Importing this module loads the shared library and raises if it is missing:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libadc.so")
+
+ADC_IP, ADC_EA = 0, 1
+ADC_OK, ADC_E_ARG, ADC_E_OOM, ADC_E_HIP, ADC_E_STATE, ADC_E_NUMERIC, ADC_E_NOCONV = (
+    0, -1, -2, -3, -4, -5, 1)
+
+# every symbol declared in include/adc.h
+ABI_SYMBOLS = ("adc_setup", "adc_set_option", "adc_set_stream", "adc_dim", "adc_diag",
+               "adc_sigma", "adc_davidson", "adc_spec_factors", "adc_set_guess",
+               "adc_last_error", "adc_destroy", "adc_last_stats")
+
+
+class ADCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i, d, ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
+    sig = {
+        "adc_setup": (i, [vp, vp, i, i, i, i, i, ctypes.POINTER(vp)]),
+        "adc_set_option": (i, [vp, ctypes.c_char_p, d]),
+        "adc_set_stream": (i, [vp, vp]),
+        "adc_dim": (ll, [vp]),
+        "adc_diag": (i, [vp, vp]),
+        "adc_sigma": (i, [vp, vp, vp, i]),
+        "adc_davidson": (i, [vp, i, vp, vp, vp, vp]),
+        "adc_spec_factors": (i, [vp, vp, i, vp, vp]),
+        "adc_set_guess": (i, [vp, vp, i]),
+        "adc_last_error": (ctypes.c_char_p, [vp]),
+        "adc_destroy": (None, [vp]),
+        "adc_last_stats": (i, [vp, vp, vp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def last_error(ctx=None) -> str:
+    return lib.adc_last_error(ctx).decode()
+
+
+def _check(rc, ctx=None, allow_noconv=False):
+    if rc == ADC_OK or (allow_noconv and rc == ADC_E_NOCONV):
+        return rc
+    raise ADCError(rc, last_error(ctx))
+
+
+def _dev(x, torch, dtype=None):
+    dtype = dtype or torch.float64
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == dtype and x.is_contiguous()):
+        raise TypeError("expected a contiguous CUDA tensor of dtype %s" % dtype)
+    return ctypes.c_void_p(x.data_ptr())
+
+
+class Context:
+    """One ADC(n) problem resident on the current GPU.
+
+    eps: [N] float64 CUDA tensor; B: [Naux, N, N] float64 CUDA tensor.
+    kind: "ea" or "ip"; order: 2 or 3.
+    """
+
+    def __init__(self, eps, B, nocc, order=2, kind="ea", stream=None):
+        import torch
+        self._torch = torch
+        self.nocc = int(nocc)
+        self.nvir = int(eps.shape[0]) - self.nocc
+        self.naux = int(B.shape[0])
+        self.order, self.kind = int(order), kind
+        h = ctypes.c_void_p()
+        k = ADC_EA if kind == "ea" else ADC_IP if kind == "ip" else -9
+        rc = lib.adc_setup(_dev(eps, torch), _dev(B, torch), self.nocc, self.nvir, self.naux,
+                           self.order, k, ctypes.byref(h))
+        _check(rc)
+        self._h = h
+        self.dim = int(lib.adc_dim(h))
+        self.nmo = self.nocc + self.nvir
+        if stream is not None:
+            self.set_stream(stream)
+
+    # ------------------------------------------------------------------
+    def set_option(self, key, value):
+        _check(lib.adc_set_option(self._h, key.encode(), float(value)), self._h)
+
+    def set_stream(self, stream):
+        ptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        _check(lib.adc_set_stream(self._h, ctypes.c_void_p(ptr)), self._h)
+
+    def diag(self):
+        torch = self._torch
+        d = torch.empty(self.dim, dtype=torch.float64, device="cuda")
+        _check(lib.adc_diag(self._h, _dev(d, torch)), self._h)
+        return d
+
+    def sigma(self, X, out=None):
+        torch = self._torch
+        X = X.reshape(-1, self.dim)
+        if out is None:
+            out = torch.empty_like(X)
+        _check(lib.adc_sigma(self._h, _dev(X, torch), _dev(out, torch), X.shape[0]), self._h)
+        return out
+
+    def davidson(self, nroots, want_vectors=True):
+        """Returns (energies [nroots], P [nroots], vectors or None, iterations, converged)."""
+        torch = self._torch
+        e = (ctypes.c_double * nroots)()
+        P = (ctypes.c_double * nroots)()
+        it = ctypes.c_int()
+        vecs = torch.empty((nroots, self.dim), dtype=torch.float64, device="cuda") \
+            if want_vectors else None
+        rc = lib.adc_davidson(self._h, int(nroots), e, P,
+                              _dev(vecs, torch) if want_vectors else None, ctypes.byref(it))
+        _check(rc, self._h, allow_noconv=True)
+        return list(e), list(P), vecs, it.value, rc == ADC_OK
+
+    def spec_factors(self, vecs):
+        torch = self._torch
+        vecs = vecs.reshape(-1, self.dim)
+        n = vecs.shape[0]
+        P = (ctypes.c_double * n)()
+        X = torch.empty((n, self.nmo), dtype=torch.float64, device="cuda")
+        _check(lib.adc_spec_factors(self._h, _dev(vecs, torch), n, P, _dev(X, torch)), self._h)
+        return list(P), X
+
+    def set_guess(self, V0):
+        torch = self._torch
+        V0 = V0.reshape(-1, self.dim)
+        _check(lib.adc_set_guess(self._h, _dev(V0, torch), V0.shape[0]), self._h)
+
+    def stats(self):
+        it, sv, mi, sec = ctypes.c_int(), ctypes.c_longlong(), ctypes.c_int(), ctypes.c_double()
+        _check(lib.adc_last_stats(self._h, ctypes.byref(it), ctypes.byref(sv), ctypes.byref(mi),
+                                  ctypes.byref(sec)), self._h)
+        return {"iters": it.value, "sigma_vectors": sv.value, "mixed_iters": mi.value,
+                "seconds": sec.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.adc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,223 @@
+// C ABI entry points: host-side argument validation, error capture, and the
+// mapping of C++ exceptions to status codes.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "context.hpp"
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(adc_ctx* c, int code, const std::string& msg) {
+    if (c)
+        c->err = msg;
+    else
+        g_err = msg;
+    return code;
+}
+
+template <typename F>
+int guarded(adc_ctx* c, F&& f) {
+    try {
+        return f();
+    } catch (const adc::Error& e) {
+        return fail(c, e.code, e.what());
+    } catch (const std::bad_alloc&) {
+        return fail(c, ADC_E_OOM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return fail(c, ADC_E_HIP, e.what());
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux, int order, int kind,
+              adc_ctx** out) {
+    if (!out) return fail(nullptr, ADC_E_ARG, "adc_setup: out is NULL");
+    *out = nullptr;
+    if (!eps || !B) return fail(nullptr, ADC_E_ARG, "adc_setup: eps or B is NULL");
+    if (nocc < 1 || nvir < 1 || naux < 1)
+        return fail(nullptr, ADC_E_ARG, "adc_setup: nocc, nvir and naux must be >= 1");
+    if (order != 2 && order != 3) return fail(nullptr, ADC_E_ARG, "adc_setup: order must be 2 or 3");
+    if (kind != ADC_IP && kind != ADC_EA)
+        return fail(nullptr, ADC_E_ARG, "adc_setup: kind must be ADC_IP or ADC_EA");
+    if ((long long)nocc + nvir > 46340)
+        return fail(nullptr, ADC_E_ARG, "adc_setup: nocc + nvir too large");
+    adc_ctx* c = new (std::nothrow) adc_ctx;
+    if (!c) return fail(nullptr, ADC_E_OOM, "adc_setup: host allocation failed");
+    c->O = nocc;
+    c->V = nvir;
+    c->Q = naux;
+    c->N = nocc + nvir;
+    c->order = order;
+    c->kind = kind;
+    if (kind == ADC_EA) {
+        c->n1 = nvir;
+        c->n2x = nocc;
+        c->n2p = nvir;
+    } else {
+        c->n1 = nocc;
+        c->n2x = nvir;
+        c->n2p = nocc;
+    }
+    c->dim = c->n1 + c->n2x * c->n2p * c->n2p;
+    c->E.scratch.arena = &c->arena;
+    int rc = guarded(nullptr, [&]() {
+        ADC_BLAS(rocblas_create_handle(&c->E.blas));
+        c->own_blas = true;
+        ADC_BLAS(rocblas_set_stream(c->E.blas, c->E.stream));
+        adc::setup_all(c, eps, B);
+        return ADC_OK;
+    });
+    if (rc != ADC_OK) {
+        adc_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return ADC_OK;
+}
+
+int adc_set_option(adc_ctx* c, const char* key, double value) {
+    if (!c) return fail(nullptr, ADC_E_ARG, "adc_set_option: NULL context");
+    if (!key) return fail(c, ADC_E_ARG, "adc_set_option: NULL key");
+    std::string k(key);
+    if (!std::isfinite(value)) return fail(c, ADC_E_ARG, "adc_set_option: value not finite");
+    if (k == "precision") {
+        if (value != 0 && value != 1) return fail(c, ADC_E_ARG, "precision must be 0 or 1");
+        c->precision = (int)value;
+    } else if (k == "block") {
+        if (value < 0 || value > 4096) return fail(c, ADC_E_ARG, "block out of range");
+        c->block = (int)value;
+    } else if (k == "max_space") {
+        if (value < 0 || value > 65536) return fail(c, ADC_E_ARG, "max_space out of range");
+        c->max_space = (int)value;
+    } else if (k == "max_iter") {
+        if (value < 1) return fail(c, ADC_E_ARG, "max_iter must be >= 1");
+        c->max_iter = (int)value;
+    } else if (k == "tol_e") {
+        if (value <= 0) return fail(c, ADC_E_ARG, "tol_e must be > 0");
+        c->tol_e = value;
+    } else if (k == "tol_r") {
+        if (value <= 0) return fail(c, ADC_E_ARG, "tol_r must be > 0");
+        c->tol_r = value;
+    } else if (k == "verbose") {
+        c->verbose = value != 0;
+    } else if (k == "workspace_limit") {
+        if (value <= 0) return fail(c, ADC_E_ARG, "workspace_limit must be > 0");
+        c->arena.limit = (size_t)value;
+    } else {
+        return fail(c, ADC_E_ARG, "adc_set_option: unknown key '" + k + "'");
+    }
+    return ADC_OK;
+}
+
+int adc_set_stream(adc_ctx* c, void* s) {
+    if (!c) return fail(nullptr, ADC_E_ARG, "adc_set_stream: NULL context");
+    return guarded(c, [&]() {
+        c->E.stream = (hipStream_t)s;
+        ADC_BLAS(rocblas_set_stream(c->E.blas, c->E.stream));
+        return ADC_OK;
+    });
+}
+
+long long adc_dim(const adc_ctx* c) { return c ? c->dim : -1; }
+
+int adc_diag(adc_ctx* c, double* d) {
+    if (!c) return fail(nullptr, ADC_E_ARG, "adc_diag: NULL context");
+    if (!d) return fail(c, ADC_E_ARG, "adc_diag: NULL output");
+    return guarded(c, [&]() {
+        ADC_HIP(hipMemcpyAsync(d, c->diag.p, c->dim * sizeof(double), hipMemcpyDeviceToDevice,
+                               c->E.stream));
+        ADC_HIP(hipStreamSynchronize(c->E.stream));
+        return ADC_OK;
+    });
+}
+
+int adc_sigma(adc_ctx* c, const double* X, double* Y, int nvec) {
+    if (!c) return fail(nullptr, ADC_E_ARG, "adc_sigma: NULL context");
+    if (!X || !Y) return fail(c, ADC_E_ARG, "adc_sigma: NULL vector");
+    if (nvec < 1) return fail(c, ADC_E_ARG, "adc_sigma: nvec must be >= 1");
+    const char* xb = (const char*)X;
+    const char* yb = (const char*)Y;
+    size_t bytes = (size_t)nvec * c->dim * sizeof(double);
+    if (xb < yb + bytes && yb < xb + bytes) return fail(c, ADC_E_ARG, "adc_sigma: X and Y overlap");
+    return guarded(c, [&]() {
+        adc::sigma(c, X, Y, nvec, c->precision);
+        ADC_HIP(hipStreamSynchronize(c->E.stream));
+        return ADC_OK;
+    });
+}
+
+int adc_davidson(adc_ctx* c, int nroots, double* energies, double* spec_factors, double* vecs,
+                 int* n_iter) {
+    if (!c) return fail(nullptr, ADC_E_ARG, "adc_davidson: NULL context");
+    if (!energies) return fail(c, ADC_E_ARG, "adc_davidson: NULL energies");
+    if (nroots < 1 || nroots > c->dim) return fail(c, ADC_E_ARG, "adc_davidson: bad nroots");
+    return guarded(c, [&]() { return adc::davidson(c, nroots, energies, spec_factors, vecs, n_iter); });
+}
+
+int adc_spec_factors(adc_ctx* c, const double* vecs, int nvec, double* P, double* X) {
+    if (!c) return fail(nullptr, ADC_E_ARG, "adc_spec_factors: NULL context");
+    if (!vecs || !P) return fail(c, ADC_E_ARG, "adc_spec_factors: NULL pointer");
+    if (nvec < 1) return fail(c, ADC_E_ARG, "adc_spec_factors: nvec must be >= 1");
+    return guarded(c, [&]() {
+        adc::DBuf<double> Xs;
+        double* Xd = X;
+        if (!Xd) {
+            Xs.alloc((size_t)nvec * c->N, &c->arena);
+            Xd = Xs.p;
+        }
+        adc::spec_amplitudes(c, vecs, nvec, Xd);
+        std::vector<double> xh((size_t)nvec * c->N);
+        ADC_HIP(hipMemcpyAsync(xh.data(), Xd, xh.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               c->E.stream));
+        ADC_HIP(hipStreamSynchronize(c->E.stream));
+        for (int k = 0; k < nvec; ++k) {
+            double s = 0.0;
+            for (int p = 0; p < c->N; ++p) s += xh[(size_t)k * c->N + p] * xh[(size_t)k * c->N + p];
+            P[k] = 2.0 * s;
+        }
+        return ADC_OK;
+    });
+}
+
+int adc_set_guess(adc_ctx* c, const double* V0, int nvec) {
+    if (!c) return fail(nullptr, ADC_E_ARG, "adc_set_guess: NULL context");
+    if (nvec < 0 || (nvec > 0 && !V0)) return fail(c, ADC_E_ARG, "adc_set_guess: bad arguments");
+    return guarded(c, [&]() {
+        c->guess.alloc((size_t)nvec * c->dim, &c->arena);
+        if (nvec)
+            ADC_HIP(hipMemcpyAsync(c->guess.p, V0, (size_t)nvec * c->dim * sizeof(double),
+                                   hipMemcpyDeviceToDevice, c->E.stream));
+        ADC_HIP(hipStreamSynchronize(c->E.stream));
+        c->nguess = nvec;
+        return ADC_OK;
+    });
+}
+
+const char* adc_last_error(const adc_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+int adc_last_stats(const adc_ctx* c, int* iters, long long* sigvec, int* mixed_iters,
+                   double* seconds) {
+    if (!c) return fail(nullptr, ADC_E_ARG, "adc_last_stats: NULL context");
+    if (iters) *iters = c->st_iters;
+    if (sigvec) *sigvec = c->st_sigvec;
+    if (mixed_iters) *mixed_iters = c->st_mixed;
+    if (seconds) *seconds = c->st_seconds;
+    return ADC_OK;
+}
+
+void adc_destroy(adc_ctx* c) {
+    if (!c) return;
+    if (c->E.stream) (void)hipStreamSynchronize(c->E.stream);
+    else (void)hipDeviceSynchronize();
+    c->E.scratch.clear();
+    if (c->own_blas && c->E.blas) rocblas_destroy_handle(c->E.blas);
+    delete c;
+}
+
+}  // extern "C"

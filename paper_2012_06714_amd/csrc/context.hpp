@@ -1,0 +1,104 @@
+// The library context: sizes, options, resident device tensors.
+#pragma once
+
+#include "adc_internal.hpp"
+
+#include <chrono>
+
+struct adc_ctx {
+    // sizes
+    int O = 0, V = 0, Q = 0, N = 0, order = 2, kind = ADC_EA;
+    long long dim = 0;     // ADC matrix dimension
+    int n1 = 0;            // 1p (EA: V) or 1h (IP: O) block size
+    long long n2x = 0;     // leading extent of the 2p1h/2h1p block (EA: O, IP: V)
+    long long n2p = 0;     // pair extent (EA: V, IP: O)
+
+    // options
+    int precision = 0;     // 0 fp64, 1 mixed
+    int block = 0;         // 0: automatic
+    int max_space = 0;     // 0: automatic
+    int max_iter = 300;
+    double tol_e = 1e-8;
+    double tol_r = -1.0;   // <0: sqrt(tol_e)
+    int verbose = 0;
+
+    adc::Arena arena;
+    adc::Engine E;
+    hipStream_t user_stream = nullptr;
+    bool own_blas = false;
+
+    // resident FP64 tensors (layouts in setup.hip)
+    adc::DBuf<double> eo, ev;
+    adc::DBuf<double> Boo, Bov, Bvv, Bvo;
+    adc::DBuf<double> ovov, oovv, ooov, oooo;
+    adc::DBuf<double> t, s, u, w;       // amplitudes
+    adc::DBuf<double> M11;              // [n1][n1]
+    adc::DBuf<double> gam;              // ADC(3) coupling intermediate [O][V] (EA: [j][b], IP: [j][b])
+    adc::DBuf<double> diag;             // [dim]
+    adc::DBuf<double> rho, om, ttu;     // spectroscopic-amplitude helpers
+    adc::DBuf<double> tt;               // t~ = 2 t_ij^ab - t_ij^ba (order 3)
+    adc::DBuf<double> Om, Pi;           // IP-ADC(3) precontracted blocks [O][O][O][V]
+    adc::DBuf<double> guess;            // warm start
+    int nguess = 0;
+
+    // mixed-precision copies (FP32)
+    adc::DBuf<float> fBov, fBvv, fBoo, fovov, foovv, ft;
+    bool mixed_ready = false;
+
+    // statistics
+    int st_iters = 0, st_mixed = 0;
+    long long st_sigvec = 0;
+    double st_seconds = 0.0;
+
+    std::string err;
+};
+
+namespace adc {
+
+// setup.hip
+void setup_all(adc_ctx* c, const double* eps, const double* B);
+void build_mixed(adc_ctx* c);
+void setup_adc3(adc_ctx* c, const double* tt, const double* X1);
+
+// sigma.hip
+template <typename T>
+void sigma_block(adc_ctx* c, const double* X, double* Y, int nvec);
+void sigma(adc_ctx* c, const double* X, double* Y, int nvec, int precision);
+
+// spec.hip
+void spec_amplitudes(adc_ctx* c, const double* vecs, int nvec, double* Xout /*device [nvec][N]*/);
+
+// davidson.hip
+int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, int* n_iter);
+
+// kernels shared by setup/sigma (elementwise.hip)
+void stage_block(Engine& E, const double* B, int Q, int N, int p0, int np, int q0, int nq,
+                 double* out);   // out[p][q][Q] = B[Q][p0+p][q0+q]
+void divide_denom2(Engine& E, double* t, const double* eo, const double* ev, int O, int V,
+                   double scale);  // t[i][j][a][b] *= scale / (e_i + e_j - e_a - e_b)
+void divide_denom1(Engine& E, double* s, const double* eo, const double* ev, int O, int V,
+                   double scale);  // s[i][a] *= scale / (e_i - e_a)
+void mul_denom2(Engine& E, const double* t, double* out, const double* eo, const double* ev, int O,
+                int V);            // out = (e_a + e_b - e_i - e_j) t
+void mul_denom1(Engine& E, const double* s, double* out, const double* eo, const double* ev, int O,
+                int V);            // out = (e_a - e_i) s
+template <typename T>
+void pair_transform(Engine& E, const T* in, long long in_stride, long long in_off, T* out,
+                    long long out_stride, long long out_off, int nvec, long long nx, int np,
+                    double al, double be, double beta_out);
+// out[z][x][p][q] = beta*out + al*in[z][x][p][q] + be*in[z][x][q][p]
+template <typename T>
+void zeroth_order(Engine& E, const T* Y, T* S, int nvec, long long nx, int np, const double* ex,
+                  const double* ep, double sx, double sp);
+// S[z][x][p][q] += (sx*ex[x] + sp*(ep[p] + ep[q])) * Y[z][x][p][q]
+void symmetrize_m11(Engine& E, double* M, const double* tau, const double* e, int n, double sgn);
+// M = sgn*diag(e) - 1/2 (tau + tau^T)
+template <typename T>
+void copy_rows(Engine& E, const T* in, long long in_stride, long long in_off, T* out,
+               long long out_stride, long long out_off, int nvec, long long len, double beta_out);
+void set_diag(Engine& E, double* d, const double* M11, int n1);
+void diag22_adc2(Engine& E, double* d, long long off, long long nx, int np, const double* ex,
+                 const double* ep, double sx, double sp);
+void diag22_first_order(adc_ctx* c, double* d);
+
+}  // namespace adc

@@ -1,0 +1,451 @@
+// Block Davidson-Liu eigensolver with an FP64 subspace (step 4 of Sec. III.A;
+// the paper uses a multiroot Davidson solver).  Basis V and sigma vectors W
+// stay on the device; the projected matrix G = V W^T is diagonalised with
+// rocSOLVER; only Ritz values and residual norms (a few hundred bytes) cross
+// to the host each iteration.
+//
+// Parameters follow this reading of the method:
+//   guesses: unit vectors at the `block` smallest diagonal entries (ties to the
+//            lower index) or the vectors given by adc_set_guess;
+//   converged when every root k < nroots has |theta_k - theta_k(prev)| <= tol_e
+//            and ||r_k|| <= tol_r;
+//   correction d = r / (theta - D) with |theta - D| floored at 1e-8;
+//   new directions are orthogonalised twice against V and orthonormalised
+//   among themselves (directions with norm below 1e-10 are dropped);
+//   restart to the current `block` Ritz vectors when V would exceed max_space.
+// Mixed precision ("precision" = 1): sigma runs in reduced precision until the
+// residuals fall below max(sqrt(tol_r), 1e-3); the space is then rebuilt from
+// the Ritz vectors with FP64 sigma and the iteration continues in FP64 to the
+// requested tolerance (iterative refinement of the reduced-precision subspace).
+#include "context.hpp"
+
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+
+namespace adc {
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+// part[k][b] = sum over chunk b of row k of x^2  (wavefront shuffles + LDS)
+__global__ void k_rownorm_part(const double* __restrict__ R, long long dim, int nchunk,
+                               double* __restrict__ part) {
+    const int k = blockIdx.y, b = blockIdx.x;
+    const long long chunk = (dim + nchunk - 1) / nchunk;
+    const long long lo = b * chunk, hi = min(dim, lo + chunk);
+    double acc = 0.0;
+    for (long long e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+        double v = R[(long long)k * dim + e];
+        acc += v * v;
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    __shared__ double red[16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+        part[(long long)k * nchunk + b] = s;
+    }
+}
+
+__global__ void k_rownorm_final(const double* part, int nchunk, int nrow, double* out) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nrow) {
+        double s = 0.0;
+        for (int b = 0; b < nchunk; ++b) s += part[(long long)k * nchunk + b];
+        out[k] = sqrt(s);
+    }
+}
+
+// R[k] = AX[k] - theta[k] X[k]
+__global__ void k_residual(const double* __restrict__ AX, const double* __restrict__ X,
+                           const double* __restrict__ theta, double* __restrict__ R, long long dim,
+                           int nb) {
+    long long total = (long long)nb * dim;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        int k = (int)(e / dim);
+        R[e] = AX[e] - theta[k] * X[e];
+    }
+}
+
+// D[k] = R[sel[k]] / (theta[sel[k]] - diag)   (|theta - diag| floored at 1e-8)
+__global__ void k_precond(const double* __restrict__ R, const double* __restrict__ diag,
+                          const double* __restrict__ theta, const int* __restrict__ sel,
+                          double* __restrict__ D, long long dim, int nsel) {
+    long long total = (long long)nsel * dim;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        int k = (int)(e / dim);
+        long long x = e - (long long)k * dim;
+        int r = sel[k];
+        double den = theta[r] - diag[x];
+        if (fabs(den) < 1e-8) den = den < 0.0 ? -1e-8 : 1e-8;
+        D[e] = R[(long long)r * dim + x] / den;
+    }
+}
+
+__global__ void k_unit(double* V, const long long* idx, long long dim, int nb) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nb) V[(long long)k * dim + idx[k]] = 1.0;
+}
+
+static unsigned nb_(long long n) {
+    long long g = (n + 255) / 256;
+    if (g > (1LL << 20)) g = 1LL << 20;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+// ---------------------------------------------------------------------------
+// small host eigensolver for the Gram matrix of a new block (cyclic Jacobi)
+// ---------------------------------------------------------------------------
+static void jacobi_eig(int n, std::vector<double>& A, std::vector<double>& w,
+                       std::vector<double>& U) {
+    U.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) U[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) off += A[(size_t)p * n + q] * A[(size_t)p * n + q];
+        if (off < 1e-30) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                double apq = A[(size_t)p * n + q];
+                if (std::fabs(apq) < 1e-300) continue;
+                double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+                double th = 0.5 * (aqq - app) / apq;
+                double tt = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                double cs = 1.0 / std::sqrt(tt * tt + 1.0), sn = tt * cs;
+                for (int k = 0; k < n; ++k) {   // rotate columns p, q
+                    double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+                    A[(size_t)k * n + p] = cs * akp - sn * akq;
+                    A[(size_t)k * n + q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < n; ++k) {   // rotate rows p, q
+                    double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+                    A[(size_t)p * n + k] = cs * apk - sn * aqk;
+                    A[(size_t)q * n + k] = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < n; ++k) {   // accumulate eigenvectors (columns)
+                    double ukp = U[(size_t)k * n + p], ukq = U[(size_t)k * n + q];
+                    U[(size_t)k * n + p] = cs * ukp - sn * ukq;
+                    U[(size_t)k * n + q] = sn * ukp + cs * ukq;
+                }
+            }
+    }
+    w.resize(n);
+    for (int i = 0; i < n; ++i) w[i] = A[(size_t)i * n + i];
+}
+
+// ---------------------------------------------------------------------------
+struct Dav {
+    adc_ctx* c;
+    Engine& E;
+    long long dim;
+    int block, max_space;
+    DBuf<double> V, W, X, AX, R, D, G, S, th, ev_e, part, rn, cmat;
+    DBuf<int> sel_d, info;
+    int nchunk = 0;
+
+    explicit Dav(adc_ctx* cc) : c(cc), E(cc->E), dim(cc->dim) {}
+
+    void rownorms(const double* M, int nrow, std::vector<double>& out) {
+        nchunk = (int)std::min<long long>(256, (dim + 4095) / 4096);
+        if (nchunk < 1) nchunk = 1;
+        part.alloc((size_t)nrow * nchunk, &c->arena);
+        rn.alloc(nrow, &c->arena);
+        hipLaunchKernelGGL(k_rownorm_part, dim3(nchunk, nrow), dim3(256), 0, E.stream, M, dim,
+                           nchunk, part.p);
+        hipLaunchKernelGGL(k_rownorm_final, dim3((nrow + 63) / 64), dim3(64), 0, E.stream, part.p,
+                           nchunk, nrow, rn.p);
+        ADC_HIP(hipGetLastError());
+        out.resize(nrow);
+        ADC_HIP(hipMemcpyAsync(out.data(), rn.p, nrow * sizeof(double), hipMemcpyDeviceToHost,
+                               E.stream));
+        ADC_HIP(hipStreamSynchronize(E.stream));
+    }
+
+    // orthogonalise nd rows of Dm against V[0:m] (twice) and among themselves;
+    // returns the number of surviving rows (compacted to the front of Dm)
+    int orthonormalize(double* Dm, int nd, int m) {
+        E.ext.Z = 0;
+        cmat.alloc((size_t)std::max(1, nd) * std::max(1, std::max(m, nd)), &c->arena);
+        for (int pass = 0; pass < 2; ++pass) {
+            if (m > 0) {
+                // C[nd][m] = Dm V^T ; Dm -= C V
+                gemm_rm<double>(E, false, true, nd, m, dim, 1.0, Dm, dim, 0, V.p, dim, 0, 0.0,
+                                cmat.p, m, 0, 1);
+                gemm_rm<double>(E, false, false, nd, dim, m, -1.0, cmat.p, m, 0, V.p, dim, 0, 1.0,
+                                Dm, dim, 0, 1);
+            }
+            // Loewdin within the block: Gram = Dm Dm^T = U w U^T ; Dm <- w^-1/2 U^T Dm
+            gemm_rm<double>(E, false, true, nd, nd, dim, 1.0, Dm, dim, 0, Dm, dim, 0, 0.0, cmat.p,
+                            nd, 0, 1);
+            std::vector<double> g((size_t)nd * nd), w, U;
+            ADC_HIP(hipMemcpyAsync(g.data(), cmat.p, g.size() * sizeof(double),
+                                   hipMemcpyDeviceToHost, E.stream));
+            ADC_HIP(hipStreamSynchronize(E.stream));
+            jacobi_eig(nd, g, w, U);
+            std::vector<int> keep;
+            for (int k = 0; k < nd; ++k)
+                if (w[k] > 1e-20) keep.push_back(k);
+            std::sort(keep.begin(), keep.end(), [&](int a, int b) { return w[a] > w[b]; });
+            int nk = (int)keep.size();
+            if (nk == 0) return 0;
+            std::vector<double> T((size_t)nk * nd);
+            for (int r = 0; r < nk; ++r)
+                for (int k = 0; k < nd; ++k)
+                    T[(size_t)r * nd + k] = U[(size_t)k * nd + keep[r]] / std::sqrt(w[keep[r]]);
+            DBuf<double> Td, tmp;
+            Td.alloc(T.size(), &c->arena);
+            tmp.alloc((size_t)nk * dim, &c->arena);
+            ADC_HIP(hipMemcpyAsync(Td.p, T.data(), T.size() * sizeof(double),
+                                   hipMemcpyHostToDevice, E.stream));
+            gemm_rm<double>(E, false, false, nk, dim, nd, 1.0, Td.p, nd, 0, Dm, dim, 0, 0.0, tmp.p,
+                            dim, 0, 1);
+            ADC_HIP(hipMemcpyAsync(Dm, tmp.p, (size_t)nk * dim * sizeof(double),
+                                   hipMemcpyDeviceToDevice, E.stream));
+            ADC_HIP(hipStreamSynchronize(E.stream));
+            nd = nk;
+        }
+        return nd;
+    }
+};
+
+int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, int* n_iter) {
+    using clk = std::chrono::steady_clock;
+    auto t0 = clk::now();
+    Engine& E = c->E;
+    const long long dim = c->dim;
+    int block = c->block > 0 ? c->block : std::max(nroots, 8);
+    block = std::max(block, nroots);
+    block = (int)std::min<long long>(block, dim);
+    int max_space = c->max_space > 0 ? c->max_space : 8 * block;
+    max_space = std::max(max_space, 2 * block);
+    max_space = (int)std::min<long long>(max_space, dim);
+    const double tol_e = c->tol_e;
+    const double tol_r = c->tol_r > 0 ? c->tol_r : std::sqrt(tol_e);
+
+    Dav d(c);
+    d.block = block;
+    d.max_space = max_space;
+    d.V.alloc((size_t)max_space * dim, &c->arena);
+    d.W.alloc((size_t)max_space * dim, &c->arena);
+    d.X.alloc((size_t)block * dim, &c->arena);
+    d.AX.alloc((size_t)block * dim, &c->arena);
+    d.R.alloc((size_t)block * dim, &c->arena);
+    d.D.alloc((size_t)block * dim, &c->arena);
+    d.G.alloc((size_t)max_space * max_space, &c->arena);
+    d.S.alloc((size_t)max_space * max_space, &c->arena);
+    d.th.alloc(max_space, &c->arena);
+    d.ev_e.alloc(max_space, &c->arena);
+    d.sel_d.alloc(block, &c->arena);
+    d.info.alloc(1, &c->arena);
+
+    // ---- initial space ----------------------------------------------------------
+    int m = 0, nb = 0;
+    if (c->nguess > 0) {
+        nb = std::min(c->nguess, block);
+        ADC_HIP(hipMemcpyAsync(d.V.p, c->guess.p, (size_t)nb * dim * sizeof(double),
+                               hipMemcpyDeviceToDevice, E.stream));
+        nb = d.orthonormalize(d.V.p, nb, 0);
+    }
+    if (nb < block) {
+        std::vector<double> dh(dim);
+        ADC_HIP(hipMemcpyAsync(dh.data(), c->diag.p, dim * sizeof(double), hipMemcpyDeviceToHost,
+                               E.stream));
+        ADC_HIP(hipStreamSynchronize(E.stream));
+        std::vector<long long> ord(dim);
+        std::iota(ord.begin(), ord.end(), 0LL);
+        int need = block - nb;
+        std::partial_sort(ord.begin(), ord.begin() + std::min<long long>(dim, need + nb), ord.end(),
+                          [&](long long a, long long b) {
+                              return dh[a] < dh[b] || (dh[a] == dh[b] && a < b);
+                          });
+        // unit vectors, orthogonalised against any guess vectors
+        double* Dm = d.V.p + (size_t)nb * dim;
+        fill<double>(E, Dm, 0.0, (size_t)need * dim);
+        DBuf<long long> idx;
+        idx.alloc(need, &c->arena);
+        ADC_HIP(hipMemcpyAsync(idx.p, ord.data(), need * sizeof(long long), hipMemcpyHostToDevice,
+                               E.stream));
+        hipLaunchKernelGGL(k_unit, dim3((need + 63) / 64), dim3(64), 0, E.stream, Dm, idx.p, dim,
+                           need);
+        ADC_HIP(hipGetLastError());
+        ADC_HIP(hipStreamSynchronize(E.stream));
+        if (nb > 0) {
+            int kept = d.orthonormalize(Dm, need, nb);
+            nb += kept;
+        } else {
+            nb = need;
+        }
+    }
+
+    std::vector<double> theta_old(block, INFINITY), theta(max_space), rnorm;
+    int it = 0, status = ADC_OK;
+    bool mixed = c->precision == 1;
+    const double tol_switch = std::max(std::sqrt(tol_r), 1e-3);
+    c->st_sigvec = 0;
+    c->st_mixed = 0;
+    int newstart = 0;    // first basis vector without a sigma vector
+    m = nb;
+    std::vector<double> Gh((size_t)max_space * max_space, 0.0);
+    std::vector<double> blk;
+    bool converged = false;
+    while (true) {
+        ++it;
+        // sigma for the new directions
+        int nn = m - newstart;
+        sigma(c, d.V.p + (size_t)newstart * dim, d.W.p + (size_t)newstart * dim, nn,
+              mixed ? 1 : 0);
+        c->st_sigvec += nn;
+        if (mixed) c->st_mixed++;
+        // G rows for the new vectors: blk[nn][m] = W_new V^T
+        {
+            DBuf<double> gb;
+            gb.alloc((size_t)nn * m, &c->arena);
+            gemm_rm<double>(E, false, true, nn, m, dim, 1.0, d.W.p + (size_t)newstart * dim, dim, 0,
+                            d.V.p, dim, 0, 0.0, gb.p, m, 0, 1);
+            blk.resize((size_t)nn * m);
+            ADC_HIP(hipMemcpyAsync(blk.data(), gb.p, blk.size() * sizeof(double),
+                                   hipMemcpyDeviceToHost, E.stream));
+            ADC_HIP(hipStreamSynchronize(E.stream));
+            for (int k = 0; k < nn; ++k) {
+                const int r = newstart + k;
+                for (int j = 0; j < newstart; ++j) {
+                    double v = blk[(size_t)k * m + j];
+                    Gh[(size_t)r * max_space + j] = v;
+                    Gh[(size_t)j * max_space + r] = v;
+                }
+                for (int j2 = 0; j2 < nn; ++j2) {
+                    const int j = newstart + j2;
+                    Gh[(size_t)r * max_space + j] =
+                        0.5 * (blk[(size_t)k * m + j] + blk[(size_t)j2 * m + r]);
+                }
+            }
+        }
+        newstart = m;
+        // projected eigenproblem (rocSOLVER, column-major == row-major for symmetric input)
+        std::vector<double> Gc((size_t)m * m);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) Gc[(size_t)i * m + j] = Gh[(size_t)i * max_space + j];
+        ADC_HIP(hipMemcpyAsync(d.S.p, Gc.data(), Gc.size() * sizeof(double),
+                               hipMemcpyHostToDevice, E.stream));
+        ADC_BLAS(rocsolver_dsyevd(E.blas, rocblas_evect_original, rocblas_fill_upper, m, d.S.p, m,
+                                  d.th.p, d.ev_e.p, d.info.p));
+        ADC_HIP(hipMemcpyAsync(theta.data(), d.th.p, m * sizeof(double), hipMemcpyDeviceToHost,
+                               E.stream));
+        int nbk = std::min(block, m);
+        // Ritz vectors: X = S^T V, AX = S^T W  (row k of S is eigenvector k)
+        gemm_rm<double>(E, false, false, nbk, dim, m, 1.0, d.S.p, m, 0, d.V.p, dim, 0, 0.0, d.X.p,
+                        dim, 0, 1);
+        gemm_rm<double>(E, false, false, nbk, dim, m, 1.0, d.S.p, m, 0, d.W.p, dim, 0, 0.0, d.AX.p,
+                        dim, 0, 1);
+        hipLaunchKernelGGL(k_residual, dim3(nb_((long long)nbk * dim)), dim3(256), 0, E.stream,
+                           d.AX.p, d.X.p, d.th.p, d.R.p, dim, nbk);
+        ADC_HIP(hipGetLastError());
+        d.rownorms(d.R.p, nbk, rnorm);
+        for (int k = 0; k < nbk; ++k)
+            if (!std::isfinite(rnorm[k]) || !std::isfinite(theta[k]))
+                throw Error(ADC_E_NUMERIC, "non-finite Ritz value or residual");
+        double maxde = 0.0, maxr = 0.0;
+        for (int k = 0; k < nroots; ++k) {
+            maxde = std::max(maxde, std::fabs(theta[k] - theta_old[k]));
+            maxr = std::max(maxr, rnorm[k]);
+        }
+        if (c->verbose) {
+            fprintf(stderr, "adc_davidson it %d m %d nbk %d %s max|dE| %.3e max|r| %.3e theta:", it, m,
+                    nbk, mixed ? "mixed" : "fp64", maxde, maxr);
+            for (int k = 0; k < nbk; ++k) fprintf(stderr, " %.10f(%.1e)", theta[k], rnorm[k]);
+            fprintf(stderr, "\n");
+        }
+        if (mixed && maxr <= tol_switch) {
+            // FP64 refinement: rebuild the space from the Ritz vectors with FP64 sigma
+            mixed = false;
+            ADC_HIP(hipMemcpyAsync(d.V.p, d.X.p, (size_t)nbk * dim * sizeof(double),
+                                   hipMemcpyDeviceToDevice, E.stream));
+            m = d.orthonormalize(d.V.p, nbk, 0);
+            newstart = 0;
+            std::fill(Gh.begin(), Gh.end(), 0.0);
+            std::fill(theta_old.begin(), theta_old.end(), INFINITY);
+            continue;
+        }
+        if (!mixed && maxde <= tol_e && maxr <= tol_r) {
+            converged = true;
+            break;
+        }
+        if (it >= c->max_iter) {
+            status = ADC_E_NOCONV;
+            break;
+        }
+        for (int k = 0; k < nbk; ++k) theta_old[k] = theta[k];
+        std::vector<int> sel;
+        double thr = mixed ? tol_switch : tol_r;
+        for (int k = 0; k < nbk; ++k)
+            if (rnorm[k] > thr) sel.push_back(k);
+        if (sel.empty())
+            for (int k = 0; k < nroots; ++k) sel.push_back(k);
+        int nsel = (int)sel.size();
+        ADC_HIP(hipMemcpyAsync(d.sel_d.p, sel.data(), nsel * sizeof(int), hipMemcpyHostToDevice,
+                               E.stream));
+        hipLaunchKernelGGL(k_precond, dim3(nb_((long long)nsel * dim)), dim3(256), 0, E.stream,
+                           d.R.p, c->diag.p, d.th.p, d.sel_d.p, d.D.p, dim, nsel);
+        ADC_HIP(hipGetLastError());
+        if (m + nsel > max_space) {
+            // restart from the current Ritz vectors
+            ADC_HIP(hipMemcpyAsync(d.V.p, d.X.p, (size_t)nbk * dim * sizeof(double),
+                                   hipMemcpyDeviceToDevice, E.stream));
+            ADC_HIP(hipMemcpyAsync(d.W.p, d.AX.p, (size_t)nbk * dim * sizeof(double),
+                                   hipMemcpyDeviceToDevice, E.stream));
+            std::fill(Gh.begin(), Gh.end(), 0.0);
+            for (int k = 0; k < nbk; ++k) Gh[(size_t)k * max_space + k] = theta[k];
+            m = nbk;
+            newstart = m;
+        }
+        int kept = d.orthonormalize(d.D.p, nsel, m);
+        if (kept == 0) {
+            // every correction lies in the current space: the space is invariant
+            // to working precision, so the Ritz pairs are converged if their
+            // residuals are
+            if (!mixed && maxr <= tol_r) converged = true;
+            else status = ADC_E_NOCONV;
+            break;
+        }
+        ADC_HIP(hipMemcpyAsync(d.V.p + (size_t)m * dim, d.D.p, (size_t)kept * dim * sizeof(double),
+                               hipMemcpyDeviceToDevice, E.stream));
+        m += kept;
+    }
+    (void)converged;
+    for (int k = 0; k < nroots; ++k) energies[k] = theta[k];
+    if (vecs)
+        ADC_HIP(hipMemcpyAsync(vecs, d.X.p, (size_t)nroots * dim * sizeof(double),
+                               hipMemcpyDeviceToDevice, E.stream));
+    if (P) {
+        DBuf<double> Xs;
+        Xs.alloc((size_t)nroots * c->N, &c->arena);
+        spec_amplitudes(c, d.X.p, nroots, Xs.p);
+        std::vector<double> xh((size_t)nroots * c->N);
+        ADC_HIP(hipMemcpyAsync(xh.data(), Xs.p, xh.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               E.stream));
+        ADC_HIP(hipStreamSynchronize(E.stream));
+        for (int k = 0; k < nroots; ++k) {
+            double s = 0.0;
+            for (int p = 0; p < c->N; ++p) s += xh[(size_t)k * c->N + p] * xh[(size_t)k * c->N + p];
+            P[k] = 2.0 * s;
+        }
+    }
+    ADC_HIP(hipStreamSynchronize(E.stream));
+    if (n_iter) *n_iter = it;
+    c->st_iters = it;
+    c->st_seconds = std::chrono::duration<double>(clk::now() - t0).count();
+    E.scratch.clear();
+    return status;
+}
+
+}  // namespace adc

@@ -1,0 +1,233 @@
+// sigma = M_Z X (step 4 of Sec. III.A) for a block of vectors.
+//
+// The spin-adapted rows of Eqs. 36-37 act on Y = S^{-1/2} Z; the result is
+// mapped back with S^{1/2} (both are 2x2 transforms on each (pq, qp) pair,
+// applied by the LDS-tiled pair kernel).  Working layouts per vector z:
+//   EA: Y1[z][a], Y2[z][i][a][b] = Y_abi   (a: attached alpha particle)
+//   IP: Y1[z][i], Y2[z][a][i][j] = Y_ija   (i: removed alpha hole)
+#include "context.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace adc {
+
+static const double SQ3 = 1.7320508075688772;
+static const double AL = 0.5 * (1.0 + SQ3), BE = 0.5 * (1.0 - SQ3);                  // S^{+1/2}
+static const double ALI = 0.5 * (1.0 + 1.0 / SQ3), BEI = 0.5 * (1.0 - 1.0 / SQ3);    // S^{-1/2}
+
+enum Slot { S_Y1 = 10, S_Y2, S_S1, S_S2, S_W, S_U, S_T1, S_T2, S_T3, S_T4 };
+
+template <typename T>
+struct Views {
+    const T *Boo, *Bov, *Bvo, *Bvv, *M11, *ovov, *oovv, *ooov, *oooo, *t, *tt, *gam, *Om, *Pi;
+};
+
+template <typename T>
+static T* slot(Engine& E, int s, size_t n) {
+    return (T*)E.scratch.get(s, n * sizeof(T));
+}
+
+// first-order coupling, zeroth-order diagonal and the 11 block (ADC(2) and up)
+template <typename T>
+static void sigma_adc2_terms(adc_ctx* c, const Views<T>& v, const T* Y1, const T* Y2, T* S1, T* S2,
+                             int nvec) {
+    Engine& E = c->E;
+    const long long Q = c->Q;
+    if (c->kind == ADC_EA) {
+        const int V = c->V;
+        // 11 block
+        ctr<T>(E, T(1), "ab", v.M11, "zb", Y1, T(0), "za", S1);
+        // 12: sigma_a += sum_bcj Y_bcj [(jb|ac) - 2 (jc|ab)]
+        T* W = slot<T>(E, S_W, (size_t)nvec * V * Q);
+        ctr<T>(E, T(1), "zjbc", Y2, "jbQ", v.Bov, T(0), "zcQ", W);
+        ctr<T>(E, T(-2), "zjcb", Y2, "jbQ", v.Bov, T(1), "zcQ", W);
+        ctr<T>(E, T(1), "acQ", v.Bvv, "zcQ", W, T(1), "za", S1);
+        // 21: sigma_abi -= sum_c Y_c (ac|bi)
+        T* U = slot<T>(E, S_U, (size_t)nvec * V * Q);
+        ctr<T>(E, T(1), "zc", Y1, "acQ", v.Bvv, T(0), "azQ", U);
+        ctr<T>(E, T(-1), "azQ", U, "ibQ", v.Bov, T(0), "ziab", S2);
+        // 22, zeroth order: (e_a + e_b - e_i) Y_abi
+        zeroth_order<T>(E, Y2, S2, nvec, c->O, V, c->eo.p, c->ev.p, -1.0, 1.0);
+    } else {
+        const int O = c->O;
+        ctr<T>(E, T(1), "ij", v.M11, "zj", Y1, T(0), "zi", S1);
+        // 12: sigma_i += sum_jkb Y_jkb [(ki|jb) - 2 (kb|ji)]
+        T* W = slot<T>(E, S_W, (size_t)nvec * O * Q);
+        ctr<T>(E, T(1), "zbjk", Y2, "bjQ", v.Bvo, T(0), "zkQ", W);
+        ctr<T>(E, T(-2), "zbkj", Y2, "bjQ", v.Bvo, T(1), "zkQ", W);
+        ctr<T>(E, T(1), "kiQ", v.Boo, "zkQ", W, T(1), "zi", S1);
+        // 21: sigma_ija -= sum_k Y_k (ki|aj)
+        T* U = slot<T>(E, S_U, (size_t)nvec * O * Q);
+        ctr<T>(E, T(1), "zk", Y1, "kiQ", v.Boo, T(0), "ziQ", U);
+        ctr<T>(E, T(-1), "ziQ", U, "jaQ", v.Bov, T(0), "zaij", S2);
+        // 22, zeroth order: (e_a - e_i - e_j) Y_ija
+        zeroth_order<T>(E, Y2, S2, nvec, c->V, O, c->ev.p, c->eo.p, 1.0, -1.0);
+    }
+}
+
+// second-order coupling and first-order 2p1h-2p1h terms of EA-ADC(3)
+// (the particle-particle term is applied separately, in the Z basis)
+template <typename T>
+static void sigma_adc3_ea_terms(adc_ctx* c, const Views<T>& v, const T* Y1, const T* Y2, T* S1,
+                                T* S2, int nvec) {
+    Engine& E = c->E;
+    const long long O = c->O, V = c->V, Q = c->Q;
+    const size_t n4 = (size_t)nvec * O * V * V;
+    const T* U = (const T*)E.scratch.get(S_U, 0);   // U[a][z][Q] = sum_c Bvv[a][c][Q] Y_c
+    T* X1 = slot<T>(E, S_T1, std::max(n4, (size_t)(nvec * O * O * O)));
+    T* X2 = slot<T>(E, S_T2, n4);
+    T* X3 = slot<T>(E, S_T3, n4);
+    T* W = slot<T>(E, S_W, (size_t)(nvec * std::max(O, V) * Q));
+    // sigma_a: -Y_bcj t_kl^bc [2 (jl|ak) - (jk|al)]
+    ctr<T>(E, T(1), "zjbc", Y2, "klbc", v.t, T(0), "zjkl", X1);
+    ctr<T>(E, T(-2), "zjkl", X1, "jlka", v.ooov, T(1), "za", S1);
+    ctr<T>(E, T(1), "zjkl", X1, "jkla", v.ooov, T(1), "za", S1);
+    // sigma_a: (Y_baj - 2 Y_abj) Gamma_jb
+    ctr<T>(E, T(1), "zjba", Y2, "jb", v.gam, T(1), "za", S1);
+    ctr<T>(E, T(-2), "zjab", Y2, "jb", v.gam, T(1), "za", S1);
+    // A~ = t~_jk^cd Y_bcj, B~ = t~_jk^cd Y_cbj, C~ = t~_jk^dc Y_cbj   ([z][b][k][d])
+    //   F1 = -2 A~ + B~ -> (dk|ab),  F2 = A~ + C~ -> (db|ak)
+    ctr<T>(E, T(1), "zjbc", Y2, "jkcd", v.tt, T(0), "zbkd", X1);        // A~
+    ctr<T>(E, T(1), "zjcb", Y2, "jkcd", v.tt, T(0), "zbkd", X2);        // B~
+    ctr<T>(E, T(1), "zjcb", Y2, "jkdc", v.tt, T(0), "zbkd", X3);        // C~
+    axpy<T>(E, T(-2), X1, X2, n4);                                      // X2 = F1
+    axpy<T>(E, T(1), X1, X3, n4);                                       // X3 = F2
+    ctr<T>(E, T(1), "zbkd", X2, "kdQ", v.Bov, T(0), "zbQ", W);
+    ctr<T>(E, T(1), "abQ", v.Bvv, "zbQ", W, T(1), "za", S1);
+    ctr<T>(E, T(1), "zbkd", X3, "bdQ", v.Bvv, T(0), "zkQ", W);
+    ctr<T>(E, T(1), "zkQ", W, "kaQ", v.Bov, T(1), "za", S1);
+    // sigma_abi from Y1 (second order)
+    ctr<T>(E, T(-1), "za", Y1, "ib", v.gam, T(1), "ziab", S2);
+    ctr<T>(E, T(1), "zc", Y1, "likc", v.ooov, T(0), "zkli", X1);
+    ctr<T>(E, T(-1), "zkli", X1, "klab", v.t, T(1), "ziab", S2);
+    ctr<T>(E, T(1), "azQ", U, "kdQ", v.Bov, T(0), "zakd", X1);          // R = (ac|kd) Y_c
+    ctr<T>(E, T(-1), "zakd", X1, "ikbd", v.tt, T(1), "ziab", S2);
+    ctr<T>(E, T(1), "zc", Y1, "kcQ", v.Bov, T(0), "zkQ", W);
+    ctr<T>(E, T(1), "zkQ", W, "adQ", v.Bvv, T(0), "zakd", X1);          // R' = (kc|ad) Y_c
+    ctr<T>(E, T(1), "zakd", X1, "ikbd", v.t, T(1), "ziab", S2);
+    ctr<T>(E, T(1), "zbkd", X1, "ikda", v.t, T(1), "ziab", S2);
+    // first-order 2p1h-2p1h: (2 Y_acj - Y_caj)(jc|ib) - Y_acj (ji|bc) - Y_cbj (ji|ac)
+    pair_transform<T>(E, Y2, (long long)(O * V * V), 0, X1, (long long)(O * V * V), 0, nvec, O,
+                      (int)V, 2.0, -1.0, 0.0);
+    ctr<T>(E, T(1), "zjac", X1, "jcib", v.ovov, T(1), "ziab", S2);
+    ctr<T>(E, T(-1), "zjac", Y2, "jibc", v.oovv, T(1), "ziab", S2);
+    ctr<T>(E, T(-1), "zjcb", Y2, "jiac", v.oovv, T(1), "ziab", S2);
+}
+
+// second-order coupling and first-order 2h1p-2h1p terms of IP-ADC(3)
+// (the hole-hole term is applied separately, in the Z basis)
+template <typename T>
+static void sigma_adc3_ip_terms(adc_ctx* c, const Views<T>& v, const T* Y1, const T* Y2, T* S1,
+                                T* S2, int nvec) {
+    Engine& E = c->E;
+    const long long O = c->O, V = c->V;
+    const size_t n3 = (size_t)(nvec * O * O * V);
+    T* X1 = slot<T>(E, S_T1, n3);
+    T* X2 = slot<T>(E, S_T2, n3);
+    // sigma_i: A~[j][l][c] = Y_jkb t~_kl^bc -> (jl|ic) - 2 (ji|lc)
+    ctr<T>(E, T(1), "zbjk", Y2, "klbc", v.tt, T(0), "zjlc", X1);
+    ctr<T>(E, T(1), "zjlc", X1, "jlic", v.ooov, T(1), "zi", S1);
+    ctr<T>(E, T(-2), "zjlc", X1, "jilc", v.ooov, T(1), "zi", S1);
+    //   Y_jkb t~_jl^bc (ki|lc) + Y_jkb t~_jl^cb (kl|ic)
+    ctr<T>(E, T(1), "zbjk", Y2, "jlbc", v.tt, T(0), "zklc", X1);
+    ctr<T>(E, T(1), "zklc", X1, "kilc", v.ooov, T(1), "zi", S1);
+    ctr<T>(E, T(1), "zbjk", Y2, "jlcb", v.tt, T(0), "zklc", X1);
+    ctr<T>(E, T(1), "zklc", X1, "klic", v.ooov, T(1), "zi", S1);
+    //   Y_jkb Omega[i][k][j][b] + (2 Y_ijb - Y_jib) Gamma_jb
+    ctr<T>(E, T(1), "zbjk", Y2, "ikjb", v.Om, T(1), "zi", S1);
+    ctr<T>(E, T(2), "zbij", Y2, "jb", v.gam, T(1), "zi", S1);
+    ctr<T>(E, T(-1), "zbji", Y2, "jb", v.gam, T(1), "zi", S1);
+    // sigma_ija from Y1 (second order)
+    ctr<T>(E, T(1), "zi", Y1, "ja", v.gam, T(1), "zaij", S2);
+    ctr<T>(E, T(1), "zk", Y1, "kilb", v.ooov, T(0), "zilb", X1);      // Z  = Y_k (ki|lb)
+    ctr<T>(E, T(-1), "zilb", X1, "jlab", v.tt, T(1), "zaij", S2);
+    ctr<T>(E, T(1), "zk", Y1, "likb", v.ooov, T(0), "zilb", X1);      // Z' = Y_k (li|kb)
+    ctr<T>(E, T(1), "zilb", X1, "jlab", v.t, T(1), "zaij", S2);
+    ctr<T>(E, T(1), "zjlb", X1, "ilba", v.t, T(1), "zaij", S2);
+    ctr<T>(E, T(-1), "zk", Y1, "kjia", v.Pi, T(1), "zaij", S2);
+    // first-order 2h1p-2h1p: (2 Y_ikb - Y_kib)(kb|ja) - Y_ikb (kj|ab) - Y_kjb (ki|ab)
+    pair_transform<T>(E, Y2, (long long)(V * O * O), 0, X2, (long long)(V * O * O), 0, nvec, V,
+                      (int)O, 2.0, -1.0, 0.0);
+    ctr<T>(E, T(1), "zbik", X2, "kbja", v.ovov, T(1), "zaij", S2);
+    ctr<T>(E, T(-1), "zbik", Y2, "kjab", v.oovv, T(1), "zaij", S2);
+    ctr<T>(E, T(-1), "zbkj", Y2, "kiab", v.oovv, T(1), "zaij", S2);
+}
+
+template <typename T>
+void vvvv_reference(adc_ctx* c, const T* Bvv, const T* in, T* out, long long nx, T beta);
+
+template <typename T>
+static Views<T> views(adc_ctx* c);
+
+template <>
+Views<double> views<double>(adc_ctx* c) {
+    return Views<double>{c->Boo.p,  c->Bov.p,  c->Bvo.p,  c->Bvv.p, c->M11.p,
+                         c->ovov.p, c->oovv.p, c->ooov.p, c->oooo.p, c->t.p,
+                         c->tt.p,   c->gam.p,  c->Om.p,   c->Pi.p};
+}
+
+template <typename T>
+void sigma_block(adc_ctx* c, const double* X, double* Yout, int nvec) {
+    Engine& E = c->E;
+    E.ext.Z = nvec;
+    const int n1 = c->n1;
+    const long long nx = c->n2x;
+    const int np = (int)c->n2p;
+    const long long len2 = nx * np * np;
+    const long long dim = c->dim;
+    Views<T> v = views<T>(c);
+
+    T* Y1 = slot<T>(E, S_Y1, (size_t)nvec * n1);
+    T* Y2 = slot<T>(E, S_Y2, (size_t)nvec * len2);
+    T* S1 = slot<T>(E, S_S1, (size_t)nvec * n1);
+    T* S2 = slot<T>(E, S_S2, (size_t)nvec * len2);
+
+    // Y = S^{-1/2} Z
+    copy_rows<double>(E, X, dim, 0, (double*)Y1, n1, 0, nvec, n1, 0.0);
+    pair_transform<double>(E, X, dim, n1, (double*)Y2, len2, 0, nvec, nx, np, ALI, BEI, 0.0);
+
+    sigma_adc2_terms<T>(c, v, Y1, Y2, S1, S2, nvec);
+    const bool ea3 = c->order == 3 && c->kind == ADC_EA;
+    const bool ip3 = c->order == 3 && c->kind == ADC_IP;
+    if (ea3) sigma_adc3_ea_terms<T>(c, v, Y1, Y2, S1, S2, nvec);
+    if (ip3) sigma_adc3_ip_terms<T>(c, v, Y1, Y2, S1, S2, nvec);
+
+    // Z-basis result: S^{1/2} sigma_Y (+ the particle-particle term, which commutes
+    // with the pair metric and acts on Z directly)
+    copy_rows<double>(E, (const double*)S1, n1, 0, Yout, dim, 0, nvec, n1, 0.0);
+    double beta2 = 0.0;
+    if (ea3) {
+        T* Zp = slot<T>(E, S_T4, (size_t)nvec * len2);
+        T* Zv = slot<T>(E, S_T1, (size_t)nvec * len2);
+        copy_rows<double>(E, X, dim, n1, (double*)Zp, len2, 0, nvec, len2, 0.0);
+        vvvv_reference<T>(c, v.Bvv, Zp, Zv, (long long)nvec * c->O, T(0));
+        copy_rows<double>(E, (const double*)Zv, len2, 0, Yout, dim, n1, nvec, len2, 0.0);
+        beta2 = 1.0;
+    }
+    if (ip3) {
+        // hole-hole term sum_kl (ki|lj) Z_kla, commutes with the pair metric
+        T* Zp = slot<T>(E, S_T4, (size_t)nvec * len2);
+        T* Zv = slot<T>(E, S_T1, (size_t)nvec * len2);
+        copy_rows<double>(E, X, dim, n1, (double*)Zp, len2, 0, nvec, len2, 0.0);
+        ctr<T>(E, T(1), "kilj", v.oooo, "zakl", Zp, T(0), "zaij", Zv);
+        copy_rows<double>(E, (const double*)Zv, len2, 0, Yout, dim, n1, nvec, len2, 0.0);
+        beta2 = 1.0;
+    }
+    pair_transform<double>(E, (const double*)S2, len2, 0, Yout, dim, n1, nvec, nx, np, AL, BE,
+                           beta2);
+}
+
+void sigma(adc_ctx* c, const double* X, double* Y, int nvec, int precision) {
+    (void)precision;
+    // process in chunks to bound the scratch footprint
+    const int chunk = 64;
+    for (int z0 = 0; z0 < nvec; z0 += chunk) {
+        int nz = nvec - z0 < chunk ? nvec - z0 : chunk;
+        sigma_block<double>(c, X + (long long)z0 * c->dim, Y + (long long)z0 * c->dim, nz);
+    }
+}
+
+template void sigma_block<double>(adc_ctx*, const double*, double*, int);
+
+}  // namespace adc

@@ -1,0 +1,291 @@
+// Tensor helpers: permutation kernel, row-major GEMM wrapper over rocBLAS and
+// an einsum-style binary contraction that maps onto (strided, batched) GEMM.
+#include "adc_internal.hpp"
+
+#include <algorithm>
+#include <cstring>
+
+namespace adc {
+
+long long Ext::of(char c) const {
+    if (c >= 'i' && c <= 'o') return O;
+    if (c >= 'a' && c <= 'h') return V;
+    if (c == 'Q') return Q;
+    if (c == 'z') return Z;
+    auto it = extra.find(c);
+    if (it == extra.end()) throw Error(ADC_E_ARG, std::string("no extent for index ") + c);
+    return it->second;
+}
+
+// ---------------------------------------------------------------------------
+// permutation
+// ---------------------------------------------------------------------------
+struct PermArgs {
+    int nd;
+    long long dim[8];      // output extents (output order)
+    long long istr[8];     // input stride of each output axis
+};
+
+template <typename T>
+__global__ void k_permute(const T* __restrict__ in, T* __restrict__ out, PermArgs a, long long total,
+                          T alpha, T beta) {
+    long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long step = (long long)gridDim.x * blockDim.x;
+    for (; o < total; o += step) {
+        long long r = o, off = 0;
+        for (int k = a.nd - 1; k >= 0; --k) {
+            long long q = r / a.dim[k];
+            off += (r - q * a.dim[k]) * a.istr[k];
+            r = q;
+        }
+        T v = alpha * in[off];
+        out[o] = (beta == T(0)) ? v : beta * out[o] + v;
+    }
+}
+
+static unsigned grid_for(long long n, int bs = 256) {
+    long long g = (n + bs - 1) / bs;
+    if (g > 65536LL * 8) g = 65536LL * 8;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+template <typename T>
+void permute(Engine& E, T alpha, const char* si, const T* in, T beta, const char* so, T* out) {
+    int nd = (int)strlen(so);
+    ADC_REQUIRE(nd == (int)strlen(si) && nd <= 8, "permute: rank mismatch");
+    long long istr_in[8];
+    long long s = 1;
+    for (int k = nd - 1; k >= 0; --k) {
+        istr_in[k] = s;
+        s *= E.ext.of(si[k]);
+    }
+    PermArgs a;
+    a.nd = nd;
+    long long total = 1;
+    for (int k = 0; k < nd; ++k) {
+        const char* p = strchr(si, so[k]);
+        ADC_REQUIRE(p, "permute: letter missing");
+        a.dim[k] = E.ext.of(so[k]);
+        a.istr[k] = istr_in[p - si];
+        total *= a.dim[k];
+    }
+    if (total == 0) return;
+    hipLaunchKernelGGL(k_permute<T>, dim3(grid_for(total)), dim3(256), 0, E.stream, in, out, a,
+                       total, alpha, beta);
+    ADC_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// GEMM (row-major view over column-major rocBLAS)
+// ---------------------------------------------------------------------------
+template <>
+void gemm_rm<double>(Engine& E, bool ta, bool tb, long long M, long long N, long long K, double alpha,
+                     const double* A, long long lda, long long sA, const double* B, long long ldb,
+                     long long sB, double beta, double* C, long long ldc, long long sC,
+                     long long batch) {
+    if (M == 0 || N == 0 || batch == 0) return;
+    E.gemm_flops += 2LL * M * N * K * batch;
+    // row-major C = op(A) op(B)  <=>  col-major C^T = op(B)^T op(A)^T
+    ADC_BLAS(rocblas_dgemm_strided_batched_64(
+        E.blas, tb ? rocblas_operation_transpose : rocblas_operation_none,
+        ta ? rocblas_operation_transpose : rocblas_operation_none, N, M, K, &alpha, B, ldb, sB, A,
+        lda, sA, &beta, C, ldc, sC, batch));
+}
+
+template <>
+void gemm_rm<float>(Engine& E, bool ta, bool tb, long long M, long long N, long long K, float alpha,
+                    const float* A, long long lda, long long sA, const float* B, long long ldb,
+                    long long sB, float beta, float* C, long long ldc, long long sC,
+                    long long batch) {
+    if (M == 0 || N == 0 || batch == 0) return;
+    E.gemm_flops += 2LL * M * N * K * batch;
+    ADC_BLAS(rocblas_sgemm_strided_batched_64(
+        E.blas, tb ? rocblas_operation_transpose : rocblas_operation_none,
+        ta ? rocblas_operation_transpose : rocblas_operation_none, N, M, K, &alpha, B, ldb, sB, A,
+        lda, sA, &beta, C, ldc, sC, batch));
+}
+
+// ---------------------------------------------------------------------------
+// einsum-style binary contraction
+// ---------------------------------------------------------------------------
+static bool has(const std::string& s, char c) { return s.find(c) != std::string::npos; }
+
+template <typename T>
+void ctr(Engine& E, T alpha, const char* sa_, const T* A, const char* sb_, const T* B, T beta,
+         const char* sc_, T* C) {
+    std::string sa(sa_), sb(sb_), sc(sc_);
+    for (char c : sa) ADC_REQUIRE(has(sb, c) || has(sc, c), "ctr: index summed in one operand");
+    for (char c : sb) ADC_REQUIRE(has(sa, c) || has(sc, c), "ctr: index summed in one operand");
+    for (char c : sc) ADC_REQUIRE(has(sa, c) || has(sb, c), "ctr: output index missing");
+    std::string batch, bcastA, bcastB, contr, fa, fb;
+    for (char c : sc)
+        if (has(sa, c) && has(sb, c)) batch += c;
+    for (char c : sa)
+        if (has(sb, c) && !has(sc, c)) contr += c;
+    // free indices keep their order in the operand they come from
+    for (char c : sa)
+        if (has(sc, c) && !has(sb, c)) fa += c;
+    for (char c : sb)
+        if (has(sc, c) && !has(sa, c)) fb += c;
+    // broadcast batching: leading free letters of an operand that also lead the
+    // output may be looped over as a batch with zero stride in the other operand
+    // (avoids permuting a large operand).
+    auto prefix_len = [](const std::string& x, const std::string& y) {
+        size_t n = 0;
+        while (n < x.size() && n < y.size() && x[n] == y[n]) ++n;
+        return n;
+    };
+    if (batch.empty()) {
+        size_t nb = prefix_len(sb, sc);
+        // only letters that are free in B
+        size_t k = 0;
+        while (k < nb && has(fb, sb[k])) ++k;
+        if (k > 0 && k < fb.size()) {
+            bcastB = sb.substr(0, k);
+            fb = fb.substr(k);
+        } else {
+            size_t na = prefix_len(sa, sc);
+            k = 0;
+            while (k < na && has(fa, sa[k])) ++k;
+            if (k > 0 && k < fa.size()) {
+                bcastA = sa.substr(0, k);
+                fa = fa.substr(k);
+            }
+        }
+    }
+    auto ext = [&](const std::string& s) {
+        long long n = 1;
+        for (char c : s) n *= E.ext.of(c);
+        return n;
+    };
+    const std::string lead = batch + bcastA + bcastB;
+    long long nbatch = ext(lead);
+    long long M = ext(fa), N = ext(fb), K = ext(contr);
+    if (nbatch == 0 || M == 0 || N == 0) return;
+
+    // operand A: [lead'][fa][contr] or [lead'][contr][fa]; lead' = batch+bcastA
+    const std::string leadA = batch + bcastA;
+    bool ta = false;
+    const T* Ause = A;
+    if (sa == leadA + fa + contr) {
+        ta = false;
+    } else if (sa == leadA + contr + fa) {
+        ta = true;
+    } else {
+        T* tmp = (T*)E.scratch.get(0, sizeof(T) * ext(sa));
+        permute<T>(E, T(1), sa.c_str(), A, T(0), (leadA + fa + contr).c_str(), tmp);
+        Ause = tmp;
+        ta = false;
+    }
+    // operand B: [lead''][contr][fb] or [lead''][fb][contr]; contr order as in A
+    const std::string leadB = batch + bcastB;
+    bool tb = false;
+    const T* Buse = B;
+    if (sb == leadB + contr + fb) {
+        tb = false;
+    } else if (sb == leadB + fb + contr) {
+        tb = true;
+    } else {
+        T* tmp = (T*)E.scratch.get(1, sizeof(T) * ext(sb));
+        permute<T>(E, T(1), sb.c_str(), B, T(0), (leadB + contr + fb).c_str(), tmp);
+        Buse = tmp;
+        tb = false;
+    }
+    long long lda = ta ? M : K, ldb = tb ? K : N;
+    long long sA = (long long)M * K, sB = (long long)K * N, sC = (long long)M * N;
+    // result layout [batch][bcastA][bcastB][fa][fb]
+    const std::string natural = batch + bcastA + bcastB + fa + fb;
+    const std::string naturalT = batch + bcastA + bcastB + fb + fa;
+    T* Cout = C;
+    bool direct = (sc == natural), directT = (sc == naturalT);
+    T beta_g = beta;
+    if (!direct && !directT) {
+        Cout = (T*)E.scratch.get(2, sizeof(T) * nbatch * M * N);
+        beta_g = T(0);
+    }
+    // batch loops: batch letters stride through both operands; broadcast letters only one
+    long long nb0 = ext(batch), nbA = ext(bcastA), nbB = ext(bcastB);
+    for (long long b0 = 0; b0 < nb0; ++b0) {
+        const T* Ab = Ause + b0 * nbA * sA;
+        const T* Bb = Buse + b0 * nbB * sB;
+        T* Cb = Cout + b0 * nbA * nbB * sC;
+        // at most one of nbA, nbB exceeds 1: loop it as the GEMM batch
+        long long nbat = nbA > 1 ? nbA : nbB;
+        long long bsA = nbA > 1 ? sA : 0, bsB = nbA > 1 ? 0 : sB;
+        if (directT) {
+            // C^T = B^T A^T
+            gemm_rm<T>(E, !tb, !ta, N, M, K, alpha, Bb, ldb, bsB, Ab, lda, bsA, beta_g, Cb, M, sC,
+                       nbat);
+        } else {
+            gemm_rm<T>(E, ta, tb, M, N, K, alpha, Ab, lda, bsA, Bb, ldb, bsB, beta_g, Cb, N, sC,
+                       nbat);
+        }
+    }
+    if (!direct && !directT) {
+        permute<T>(E, T(1), natural.c_str(), Cout, beta, sc.c_str(), C);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// elementwise
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill(T* p, T v, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+template <typename T>
+__global__ void k_axpy(T a, const T* x, T* y, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        y[i] += a * x[i];
+}
+__global__ void k_d2f(const double* in, float* out, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        out[i] = (float)in[i];
+}
+__global__ void k_f2d(const float* in, double* out, size_t n, double beta) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        out[i] = (beta == 0.0 ? 0.0 : beta * out[i]) + (double)in[i];
+}
+
+template <typename T>
+void fill(Engine& E, T* p, T v, size_t n) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(256), 0, E.stream, p, v, n);
+    ADC_HIP(hipGetLastError());
+}
+template <typename T>
+void axpy(Engine& E, T a, const T* x, T* y, size_t n) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_axpy<T>, dim3(grid_for(n)), dim3(256), 0, E.stream, a, x, y, n);
+    ADC_HIP(hipGetLastError());
+}
+void convert_d2f(Engine& E, const double* in, float* out, size_t n) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_d2f, dim3(grid_for(n)), dim3(256), 0, E.stream, in, out, n);
+    ADC_HIP(hipGetLastError());
+}
+void convert_f2d(Engine& E, const float* in, double* out, size_t n, double beta) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_f2d, dim3(grid_for(n)), dim3(256), 0, E.stream, in, out, n, beta);
+    ADC_HIP(hipGetLastError());
+}
+
+template void ctr<double>(Engine&, double, const char*, const double*, const char*, const double*,
+                          double, const char*, double*);
+template void ctr<float>(Engine&, float, const char*, const float*, const char*, const float*,
+                         float, const char*, float*);
+template void permute<double>(Engine&, double, const char*, const double*, double, const char*,
+                              double*);
+template void permute<float>(Engine&, float, const char*, const float*, float, const char*, float*);
+template void fill<double>(Engine&, double*, double, size_t);
+template void fill<float>(Engine&, float*, float, size_t);
+template void axpy<double>(Engine&, double, const double*, double*, size_t);
+template void axpy<float>(Engine&, float, const float*, float*, size_t);
+
+}  // namespace adc
