@@ -132,6 +132,29 @@ int adc_spec_factors(adc_ctx* ctx, const double* vecs, int nvec, double* P, doub
  * (device [nvec][dim], copied). */
 int adc_set_guess(adc_ctx* ctx, const double* V0, int nvec);
 
+/* Convergence history of the last adc_davidson call: for each iteration k <
+ * min(count, max_entries): seconds[k] since the call started (host wall
+ * clock after the iteration's Ritz values were known), theta[k*nroots + r]
+ * and rnorm[k*nroots + r] for the lowest nroots Ritz pairs, and mixed[k] = 1
+ * for a reduced-precision iteration.  Any output may be NULL.  Returns the
+ * number of recorded iterations (>= 0) or a negative error code. */
+int adc_history(const adc_ctx* ctx, int max_entries, double* seconds, double* theta,
+                double* rnorm, int* mixed);
+
+/* Algorithmic cost model of one adc_sigma call on nvec vectors (Table I
+ * scaling with the constants of this implementation; 2 flops per
+ * multiply-add).  total: every contraction of the call; pp: the
+ * particle-particle / hole-hole term alone (EA-ADC(3): the rebuild of the
+ * unique (ac|bd), Naux V^2 (V^2+1), plus 2 O V^4 nvec; IP-ADC(3):
+ * 2 V O^4 nvec; 0 for ADC(2)).  Host outputs; never touches the device. */
+int adc_sigma_flops(const adc_ctx* ctx, int nvec, double* total, double* pp);
+
+/* adc_sigma with timing: HIP events recorded on the context's stream
+ * around the particle-particle kernel(s) and around the whole call.
+ * ms_pp, ms_total: host outputs in milliseconds (either may be NULL). */
+int adc_sigma_timed(adc_ctx* ctx, const double* X, double* Y, int nvec, double* ms_pp,
+                    double* ms_total);
+
 /* Message describing the last failure of ctx (or of a call that had no
  * context when ctx is NULL).  Never NULL; owned by the library. */
 const char* adc_last_error(const adc_ctx* ctx);

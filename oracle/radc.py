@@ -63,7 +63,7 @@ def _parse(spec):
 class RADC:
     """CPU FP64 spin-adapted ADC(n), n in {2, 3}, kind in {"ea", "ip"}."""
 
-    def __init__(self, eps, B, nocc, order, kind):
+    def __init__(self, eps, B, nocc, order, kind, lazy=False):
         eps = np.asarray(eps, dtype=np.float64)
         B = np.asarray(B, dtype=np.float64)
         if order not in (2, 3) or kind not in ("ea", "ip"):
@@ -79,10 +79,20 @@ class RADC:
                    ("v", "v"): np.ascontiguousarray(B[:, v, v])}
         self.terms = radc_terms.EA_TERMS if kind == "ea" else radc_terms.IP_TERMS
         self.T = {"f": None}
-        self._amplitudes()
         self.dim = (V + O * V * V) if kind == "ea" else (O + O * O * V)
         self.n1 = V if kind == "ea" else O
-        self.M11 = self._m11()
+        self._amplitudes()
+        self._M11 = None
+        if not lazy:            # lazy: third-order amplitudes and M11 on first use
+            self._third_order()
+            self._M11 = self._m11()
+
+    @property
+    def M11(self):
+        if self._M11 is None:
+            self._third_order()
+            self._M11 = self._m11()
+        return self._M11
 
     # ------------------------------------------------------------------
     # term evaluation
@@ -118,6 +128,8 @@ class RADC:
                 subs.append("z" + idx)
                 ops.append(Y2)
             else:
+                if name not in self.T:
+                    self._third_order()
                 subs.append(idx)
                 ops.append(self.T[name])
         return subs, ops
@@ -126,8 +138,7 @@ class RADC:
         acc = None
         for coef, spec in terms:
             subs, ops = self._operands(spec, **kw)
-            val = float(eval_fraction(coef)) * np.einsum(
-                ",".join(subs) + "->" + out, *ops, optimize="greedy")
+            val = float(eval_fraction(coef)) * _einsum_sliced(subs, out, ops)
             acc = val if acc is None else acc + val
         return acc
 
@@ -145,11 +156,16 @@ class RADC:
         amp = radc_terms.AMP_TERMS
         self.T["s"] = -self._eval(amp["t1_2"], "ia") / D1
         self.T["Ds"] = D1 * self.T["s"]
-        if self.order >= 3:
-            self.T["u"] = -self._eval(amp["t2_2"], "ijab") / D2
-            self.T["Du"] = D2 * self.T["u"]
-            self.T["w"] = -self._eval(amp["t1_3"], "ia") / D1
         self.D1, self.D2 = D1, D2
+
+    def _third_order(self):
+        """Second-order doubles u and third-order singles w (order 3 only)."""
+        if self.order < 3 or "u" in self.T:
+            return
+        amp = radc_terms.AMP_TERMS
+        self.T["u"] = -self._eval(amp["t2_2"], "ijab") / self.D2
+        self.T["Du"] = self.D2 * self.T["u"]
+        self.T["w"] = -self._eval(amp["t1_3"], "ia") / self.D1
 
     def mp_energy(self, k):
         """k-th order correlation energy: E(2) from t, E(3) from u (closed shell)."""
@@ -207,22 +223,28 @@ class RADC:
     # ------------------------------------------------------------------
     # step 4: sigma = M Z
     # ------------------------------------------------------------------
-    def sigma_y(self, Y1, Y2):
-        """Rows of M_Y Y (the non-symmetric representation of Eqs. 36-37)."""
+    def sigma_y(self, Y1, Y2, skip_11=False):
+        """Rows of M_Y Y (the non-symmetric representation of Eqs. 36-37).
+
+        skip_11 leaves out the 1p-1p / 1h-1h product (used to time the rest
+        without building M11)."""
         if self.kind == "ea":
             e1, e2 = "za", "zabi"
         else:
             e1, e2 = "zi", "zija"
-        s1 = np.einsum("xy,zy->zx", self.M11, Y1)
+        if skip_11:
+            s1 = np.zeros_like(Y1)
+        else:
+            s1 = np.einsum("xy,zy->zx", self.M11, Y1)
         s1 = s1 + self._eval(self._blocks("12"), e1, Y1=Y1, Y2=Y2)
         s2 = self._eval(self._blocks("21") + self._blocks("22"), e2, Y1=Y1, Y2=Y2)
         return s1, s2
 
-    def sigma(self, vecs):
+    def sigma(self, vecs, skip_11=False):
         """sigma = M_Z X for X [nvec, dim] (boundary layout)."""
         Z1, Z2 = self.unpack(vecs)
         Y2 = self.z_to_y(Z2)
-        s1, s2 = self.sigma_y(Z1, Y2)
+        s1, s2 = self.sigma_y(Z1, Y2, skip_11=skip_11)
         return self.pack(s1, self.y_to_z(s2))
 
     def explicit(self):
@@ -284,7 +306,7 @@ class RADC:
                 if c not in used:     # value independent of this index
                     subs.append(c)
                     ops.append(np.ones(self.O if _space(c) == "o" else self.V))
-            val = np.einsum(",".join(subs) + "->" + uniq, *ops, optimize="greedy")
+            val = np.einsum(",".join(subs) + "->" + uniq, *ops, optimize="optimal")
             view = _diag_view(out, outl, uniq)
             view += float(eval_fraction(coef)) * val
         return out
@@ -319,6 +341,47 @@ class RADC:
         """P = 2 sum_p X_p^2 (Eq. 50) for normalised vectors in the Z basis."""
         X = self.spec_amplitudes(vecs)
         return 2.0 * np.sum(X * X, axis=1)
+
+
+# Largest intermediate (elements) a single einsum step may create; bigger terms
+# are evaluated slice by slice along an output index (the same sum, split over
+# the values of one free index).
+EINSUM_LIMIT = 2.0e8
+
+
+def _einsum_sliced(subs, out, ops):
+    expr = ",".join(subs) + "->" + out
+    path, info = np.einsum_path(expr, *ops, optimize=("optimal", 1e30))
+    biggest = 0.0
+    for line in info.split("\n"):
+        if line.strip().startswith("Largest intermediate"):
+            biggest = float(line.split(":")[1].split()[0])
+    if biggest <= EINSUM_LIMIT or not out:
+        return np.einsum(expr, *ops, optimize=path)
+    # split along the output index with the largest extent
+    sizes = {}
+    for sub, op in zip(subs, ops):
+        for c, n in zip(sub, op.shape):
+            sizes[c] = n
+    ax = max(out, key=lambda c: sizes[c])
+    n = sizes[ax]
+    if n <= 1:
+        return np.einsum(expr, *ops, optimize=path)
+    nchunk = int(min(n, np.ceil(biggest / EINSUM_LIMIT)))
+    bounds = np.linspace(0, n, nchunk + 1).astype(int)
+    parts = []
+    for lo, hi in zip(bounds[:-1], bounds[1:]):
+        sops = []
+        for sub, op in zip(subs, ops):
+            if ax in sub:
+                sl = [slice(None)] * op.ndim
+                for k, c in enumerate(sub):
+                    if c == ax:
+                        sl[k] = slice(lo, hi)
+                op = op[tuple(sl)]
+            sops.append(op)
+        parts.append(_einsum_sliced(subs, out, sops))
+    return np.concatenate(parts, axis=out.index(ax))
 
 
 def _diag_view(arr, letters, uniq):

@@ -20,7 +20,8 @@ ADC_OK, ADC_E_ARG, ADC_E_OOM, ADC_E_HIP, ADC_E_STATE, ADC_E_NUMERIC, ADC_E_NOCON
 # every symbol declared in include/adc.h
 ABI_SYMBOLS = ("adc_setup", "adc_set_option", "adc_set_stream", "adc_dim", "adc_diag",
                "adc_sigma", "adc_davidson", "adc_spec_factors", "adc_set_guess",
-               "adc_last_error", "adc_destroy", "adc_last_stats")
+               "adc_last_error", "adc_destroy", "adc_last_stats", "adc_sigma_flops",
+               "adc_sigma_timed", "adc_history")
 
 
 class ADCError(RuntimeError):
@@ -47,6 +48,9 @@ def _load():
         "adc_last_error": (ctypes.c_char_p, [vp]),
         "adc_destroy": (None, [vp]),
         "adc_last_stats": (i, [vp, vp, vp, vp, vp]),
+        "adc_sigma_flops": (i, [vp, i, vp, vp]),
+        "adc_sigma_timed": (i, [vp, vp, vp, i, vp, vp]),
+        "adc_history": (i, [vp, i, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -148,6 +152,38 @@ class Context:
         torch = self._torch
         V0 = V0.reshape(-1, self.dim)
         _check(lib.adc_set_guess(self._h, _dev(V0, torch), V0.shape[0]), self._h)
+
+    def sigma_flops(self, nvec):
+        t, p = ctypes.c_double(), ctypes.c_double()
+        _check(lib.adc_sigma_flops(self._h, int(nvec), ctypes.byref(t), ctypes.byref(p)), self._h)
+        return t.value, p.value
+
+    def sigma_timed(self, X, out=None):
+        """sigma with HIP-event timing: returns (Y, ms_pp, ms_total)."""
+        torch = self._torch
+        X = X.reshape(-1, self.dim)
+        if out is None:
+            out = torch.empty_like(X)
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(lib.adc_sigma_timed(self._h, _dev(X, torch), _dev(out, torch), X.shape[0],
+                                   ctypes.byref(a), ctypes.byref(b)), self._h)
+        return out, a.value, b.value
+
+    def history(self, nroots, max_entries=100000):
+        """(seconds [n], theta [n, nroots], rnorm [n, nroots], mixed [n]) of the last solve."""
+        import numpy as np
+        n = lib.adc_history(self._h, 0, None, None, None, None)
+        if n < 0:
+            _check(n, self._h)
+        n = min(n, max_entries)
+        t = np.zeros(n)
+        th = np.zeros((n, nroots))
+        r = np.zeros((n, nroots))
+        mx = np.zeros(n, dtype=np.int32)
+        lib.adc_history(self._h, n, t.ctypes.data_as(ctypes.c_void_p),
+                        th.ctypes.data_as(ctypes.c_void_p), r.ctypes.data_as(ctypes.c_void_p),
+                        mx.ctypes.data_as(ctypes.c_void_p))
+        return t, th, r, mx
 
     def stats(self):
         it, sv, mi, sec = ctypes.c_int(), ctypes.c_longlong(), ctypes.c_int(), ctypes.c_double()

@@ -138,6 +138,8 @@ struct Engine {
     Scratch scratch;
     Ext ext;
     long long gemm_flops = 0;
+    bool timing = false;     // record events around the particle-particle kernels
+    double pp_ms = 0.0;      // accumulated milliseconds of those kernels
 };
 
 template <typename T>

@@ -199,6 +199,59 @@ int adc_set_guess(adc_ctx* c, const double* V0, int nvec) {
     });
 }
 
+int adc_history(const adc_ctx* c, int max_entries, double* seconds, double* theta, double* rnorm,
+                int* mixed) {
+    if (!c) return fail(nullptr, ADC_E_ARG, "adc_history: NULL context");
+    int n = (int)c->hist_t.size();
+    int m = max_entries < n ? max_entries : n;
+    int nr = c->hist_nroots;
+    for (int k = 0; k < m; ++k) {
+        if (seconds) seconds[k] = c->hist_t[k];
+        if (mixed) mixed[k] = c->hist_mixed[k];
+        for (int r = 0; r < nr; ++r) {
+            if (theta) theta[(size_t)k * nr + r] = c->hist_theta[(size_t)k * nr + r];
+            if (rnorm) rnorm[(size_t)k * nr + r] = c->hist_r[(size_t)k * nr + r];
+        }
+    }
+    return n;
+}
+
+int adc_sigma_flops(const adc_ctx* c, int nvec, double* total, double* pp) {
+    if (!c) return fail(nullptr, ADC_E_ARG, "adc_sigma_flops: NULL context");
+    if (nvec < 1) return fail(const_cast<adc_ctx*>(c), ADC_E_ARG, "adc_sigma_flops: nvec < 1");
+    double t = 0.0, p = 0.0;
+    adc::sigma_cost(c, nvec, &t, &p);
+    if (total) *total = t;
+    if (pp) *pp = p;
+    return ADC_OK;
+}
+
+int adc_sigma_timed(adc_ctx* c, const double* X, double* Y, int nvec, double* ms_pp,
+                    double* ms_total) {
+    if (!c) return fail(nullptr, ADC_E_ARG, "adc_sigma_timed: NULL context");
+    if (!X || !Y) return fail(c, ADC_E_ARG, "adc_sigma_timed: NULL vector");
+    if (nvec < 1) return fail(c, ADC_E_ARG, "adc_sigma_timed: nvec must be >= 1");
+    return guarded(c, [&]() {
+        hipEvent_t e0, e1;
+        ADC_HIP(hipEventCreate(&e0));
+        ADC_HIP(hipEventCreate(&e1));
+        c->E.pp_ms = 0.0;
+        c->E.timing = true;
+        ADC_HIP(hipEventRecord(e0, c->E.stream));
+        adc::sigma(c, X, Y, nvec, c->precision);
+        ADC_HIP(hipEventRecord(e1, c->E.stream));
+        ADC_HIP(hipEventSynchronize(e1));
+        c->E.timing = false;
+        float ms = 0.f;
+        ADC_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms_total) *ms_total = ms;
+        if (ms_pp) *ms_pp = c->E.pp_ms;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return ADC_OK;
+    });
+}
+
 const char* adc_last_error(const adc_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
 
 int adc_last_stats(const adc_ctx* c, int* iters, long long* sigvec, int* mixed_iters,

@@ -45,7 +45,10 @@ struct adc_ctx {
     adc::DBuf<float> fBov, fBvv, fBoo, fovov, foovv, ft;
     bool mixed_ready = false;
 
-    // statistics
+    // statistics and convergence history of the last solve
+    int hist_nroots = 0;
+    std::vector<double> hist_t, hist_theta, hist_r;
+    std::vector<int> hist_mixed;
     int st_iters = 0, st_mixed = 0;
     long long st_sigvec = 0;
     double st_seconds = 0.0;
@@ -64,6 +67,7 @@ void setup_adc3(adc_ctx* c, const double* tt, const double* X1);
 template <typename T>
 void sigma_block(adc_ctx* c, const double* X, double* Y, int nvec);
 void sigma(adc_ctx* c, const double* X, double* Y, int nvec, int precision);
+void sigma_cost(const adc_ctx* c, int nvec, double* total, double* pp);
 
 // spec.hip
 void spec_amplitudes(adc_ctx* c, const double* vecs, int nvec, double* Xout /*device [nvec][N]*/);

@@ -10,8 +10,8 @@
 //   converged when every root k < nroots has |theta_k - theta_k(prev)| <= tol_e
 //            and ||r_k|| <= tol_r;
 //   correction d = r / (theta - D) with |theta - D| floored at 1e-8;
-//   new directions are orthogonalised twice against V and orthonormalised
-//   among themselves (directions with norm below 1e-10 are dropped);
+//   each new direction is orthogonalised twice against V and the directions
+//   already accepted, and dropped if its norm falls below 1e-10;
 //   restart to the current `block` Ritz vectors when V would exceed max_space.
 // Mixed precision ("precision" = 1): sigma runs in reduced precision until the
 // residuals fall below max(sqrt(tol_r), 1e-3); the space is then rebuilt from
@@ -91,6 +91,12 @@ __global__ void k_precond(const double* __restrict__ R, const double* __restrict
     }
 }
 
+__global__ void k_scale(double* x, double a, long long n) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (long long)gridDim.x * blockDim.x)
+        x[e] *= a;
+}
+
 __global__ void k_unit(double* V, const long long* idx, long long dim, int nb) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < nb) V[(long long)k * dim + idx[k]] = 1.0;
@@ -100,47 +106,6 @@ static unsigned nb_(long long n) {
     long long g = (n + 255) / 256;
     if (g > (1LL << 20)) g = 1LL << 20;
     return (unsigned)(g < 1 ? 1 : g);
-}
-
-// ---------------------------------------------------------------------------
-// small host eigensolver for the Gram matrix of a new block (cyclic Jacobi)
-// ---------------------------------------------------------------------------
-static void jacobi_eig(int n, std::vector<double>& A, std::vector<double>& w,
-                       std::vector<double>& U) {
-    U.assign((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) U[(size_t)i * n + i] = 1.0;
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        double off = 0.0;
-        for (int p = 0; p < n; ++p)
-            for (int q = p + 1; q < n; ++q) off += A[(size_t)p * n + q] * A[(size_t)p * n + q];
-        if (off < 1e-30) break;
-        for (int p = 0; p < n; ++p)
-            for (int q = p + 1; q < n; ++q) {
-                double apq = A[(size_t)p * n + q];
-                if (std::fabs(apq) < 1e-300) continue;
-                double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
-                double th = 0.5 * (aqq - app) / apq;
-                double tt = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
-                double cs = 1.0 / std::sqrt(tt * tt + 1.0), sn = tt * cs;
-                for (int k = 0; k < n; ++k) {   // rotate columns p, q
-                    double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
-                    A[(size_t)k * n + p] = cs * akp - sn * akq;
-                    A[(size_t)k * n + q] = sn * akp + cs * akq;
-                }
-                for (int k = 0; k < n; ++k) {   // rotate rows p, q
-                    double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
-                    A[(size_t)p * n + k] = cs * apk - sn * aqk;
-                    A[(size_t)q * n + k] = sn * apk + cs * aqk;
-                }
-                for (int k = 0; k < n; ++k) {   // accumulate eigenvectors (columns)
-                    double ukp = U[(size_t)k * n + p], ukq = U[(size_t)k * n + q];
-                    U[(size_t)k * n + p] = cs * ukp - sn * ukq;
-                    U[(size_t)k * n + q] = sn * ukp + cs * ukq;
-                }
-            }
-    }
-    w.resize(n);
-    for (int i = 0; i < n; ++i) w[i] = A[(size_t)i * n + i];
 }
 
 // ---------------------------------------------------------------------------
@@ -171,50 +136,44 @@ struct Dav {
         ADC_HIP(hipStreamSynchronize(E.stream));
     }
 
-    // orthogonalise nd rows of Dm against V[0:m] (twice) and among themselves;
-    // returns the number of surviving rows (compacted to the front of Dm)
+    // orthogonalise nd rows of Dm against V[0:m] and against the rows already
+    // accepted (two classical Gram-Schmidt passes per row), drop rows whose norm
+    // falls below 1e-10, normalise the rest; returns the number kept (compacted
+    // to the front of Dm)
     int orthonormalize(double* Dm, int nd, int m) {
-        E.ext.Z = 0;
-        cmat.alloc((size_t)std::max(1, nd) * std::max(1, std::max(m, nd)), &c->arena);
-        for (int pass = 0; pass < 2; ++pass) {
-            if (m > 0) {
-                // C[nd][m] = Dm V^T ; Dm -= C V
-                gemm_rm<double>(E, false, true, nd, m, dim, 1.0, Dm, dim, 0, V.p, dim, 0, 0.0,
-                                cmat.p, m, 0, 1);
-                gemm_rm<double>(E, false, false, nd, dim, m, -1.0, cmat.p, m, 0, V.p, dim, 0, 1.0,
-                                Dm, dim, 0, 1);
+        cmat.alloc((size_t)std::max(1, m + nd), &c->arena);
+        int kept = 0;
+        std::vector<double> nrm;
+        for (int k = 0; k < nd; ++k) {
+            double* dk = Dm + (size_t)k * dim;
+            double* out = Dm + (size_t)kept * dim;
+            if (k != kept)
+                ADC_HIP(hipMemcpyAsync(out, dk, dim * sizeof(double), hipMemcpyDeviceToDevice,
+                                       E.stream));
+            for (int pass = 0; pass < 2; ++pass) {
+                if (m > 0) {
+                    gemm_rm<double>(E, false, true, 1, m, dim, 1.0, out, dim, 0, V.p, dim, 0, 0.0,
+                                    cmat.p, m, 0, 1);
+                    gemm_rm<double>(E, false, false, 1, dim, m, -1.0, cmat.p, m, 0, V.p, dim, 0,
+                                    1.0, out, dim, 0, 1);
+                }
+                if (kept > 0) {
+                    gemm_rm<double>(E, false, true, 1, kept, dim, 1.0, out, dim, 0, Dm, dim, 0, 0.0,
+                                    cmat.p, kept, 0, 1);
+                    gemm_rm<double>(E, false, false, 1, dim, kept, -1.0, cmat.p, kept, 0, Dm, dim,
+                                    0, 1.0, out, dim, 0, 1);
+                }
             }
-            // Loewdin within the block: Gram = Dm Dm^T = U w U^T ; Dm <- w^-1/2 U^T Dm
-            gemm_rm<double>(E, false, true, nd, nd, dim, 1.0, Dm, dim, 0, Dm, dim, 0, 0.0, cmat.p,
-                            nd, 0, 1);
-            std::vector<double> g((size_t)nd * nd), w, U;
-            ADC_HIP(hipMemcpyAsync(g.data(), cmat.p, g.size() * sizeof(double),
-                                   hipMemcpyDeviceToHost, E.stream));
-            ADC_HIP(hipStreamSynchronize(E.stream));
-            jacobi_eig(nd, g, w, U);
-            std::vector<int> keep;
-            for (int k = 0; k < nd; ++k)
-                if (w[k] > 1e-20) keep.push_back(k);
-            std::sort(keep.begin(), keep.end(), [&](int a, int b) { return w[a] > w[b]; });
-            int nk = (int)keep.size();
-            if (nk == 0) return 0;
-            std::vector<double> T((size_t)nk * nd);
-            for (int r = 0; r < nk; ++r)
-                for (int k = 0; k < nd; ++k)
-                    T[(size_t)r * nd + k] = U[(size_t)k * nd + keep[r]] / std::sqrt(w[keep[r]]);
-            DBuf<double> Td, tmp;
-            Td.alloc(T.size(), &c->arena);
-            tmp.alloc((size_t)nk * dim, &c->arena);
-            ADC_HIP(hipMemcpyAsync(Td.p, T.data(), T.size() * sizeof(double),
-                                   hipMemcpyHostToDevice, E.stream));
-            gemm_rm<double>(E, false, false, nk, dim, nd, 1.0, Td.p, nd, 0, Dm, dim, 0, 0.0, tmp.p,
-                            dim, 0, 1);
-            ADC_HIP(hipMemcpyAsync(Dm, tmp.p, (size_t)nk * dim * sizeof(double),
-                                   hipMemcpyDeviceToDevice, E.stream));
-            ADC_HIP(hipStreamSynchronize(E.stream));
-            nd = nk;
+            rownorms(out, 1, nrm);
+            if (nrm[0] > 1e-10 && std::isfinite(nrm[0])) {
+                hipLaunchKernelGGL(k_scale, dim3(nb_(dim)), dim3(256), 0, E.stream, out,
+                                   1.0 / nrm[0], dim);
+                ADC_HIP(hipGetLastError());
+                ++kept;
+            }
         }
-        return nd;
+        ADC_HIP(hipStreamSynchronize(E.stream));
+        return kept;
     }
 };
 
@@ -296,6 +255,11 @@ int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, 
     int newstart = 0;    // first basis vector without a sigma vector
     m = nb;
     std::vector<double> Gh((size_t)max_space * max_space, 0.0);
+    c->hist_nroots = nroots;
+    c->hist_t.clear();
+    c->hist_theta.clear();
+    c->hist_r.clear();
+    c->hist_mixed.clear();
     std::vector<double> blk;
     bool converged = false;
     while (true) {
@@ -354,6 +318,12 @@ int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, 
         for (int k = 0; k < nbk; ++k)
             if (!std::isfinite(rnorm[k]) || !std::isfinite(theta[k]))
                 throw Error(ADC_E_NUMERIC, "non-finite Ritz value or residual");
+        c->hist_t.push_back(std::chrono::duration<double>(clk::now() - t0).count());
+        for (int k = 0; k < nroots; ++k) {
+            c->hist_theta.push_back(k < nbk ? theta[k] : NAN);
+            c->hist_r.push_back(k < nbk ? rnorm[k] : NAN);
+        }
+        c->hist_mixed.push_back(mixed ? 1 : 0);
         double maxde = 0.0, maxr = 0.0;
         for (int k = 0; k < nroots; ++k) {
             maxde = std::max(maxde, std::fabs(theta[k] - theta_old[k]));

@@ -23,6 +23,33 @@ struct Views {
     const T *Boo, *Bov, *Bvo, *Bvv, *M11, *ovov, *oovv, *ooov, *oooo, *t, *tt, *gam, *Om, *Pi;
 };
 
+// HIP events around the particle-particle (hole-hole) kernels when timing is on
+struct PPTimer {
+    Engine& E;
+    hipEvent_t a = nullptr, b = nullptr;
+    explicit PPTimer(Engine& e) : E(e) {
+        if (!E.timing) return;
+        ADC_HIP(hipEventCreate(&a));
+        ADC_HIP(hipEventCreate(&b));
+        ADC_HIP(hipEventRecord(a, E.stream));
+    }
+    void stop() {
+        if (!a) return;
+        ADC_HIP(hipEventRecord(b, E.stream));
+        ADC_HIP(hipEventSynchronize(b));
+        float ms = 0.f;
+        ADC_HIP(hipEventElapsedTime(&ms, a, b));
+        E.pp_ms += ms;
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        a = b = nullptr;
+    }
+    ~PPTimer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
 template <typename T>
 static T* slot(Engine& E, int s, size_t n) {
     return (T*)E.scratch.get(s, n * sizeof(T));
@@ -201,7 +228,9 @@ void sigma_block(adc_ctx* c, const double* X, double* Yout, int nvec) {
         T* Zp = slot<T>(E, S_T4, (size_t)nvec * len2);
         T* Zv = slot<T>(E, S_T1, (size_t)nvec * len2);
         copy_rows<double>(E, X, dim, n1, (double*)Zp, len2, 0, nvec, len2, 0.0);
+        PPTimer tm(E);
         vvvv_reference<T>(c, v.Bvv, Zp, Zv, (long long)nvec * c->O, T(0));
+        tm.stop();
         copy_rows<double>(E, (const double*)Zv, len2, 0, Yout, dim, n1, nvec, len2, 0.0);
         beta2 = 1.0;
     }
@@ -210,7 +239,9 @@ void sigma_block(adc_ctx* c, const double* X, double* Yout, int nvec) {
         T* Zp = slot<T>(E, S_T4, (size_t)nvec * len2);
         T* Zv = slot<T>(E, S_T1, (size_t)nvec * len2);
         copy_rows<double>(E, X, dim, n1, (double*)Zp, len2, 0, nvec, len2, 0.0);
+        PPTimer tm(E);
         ctr<T>(E, T(1), "kilj", v.oooo, "zakl", Zp, T(0), "zaij", Zv);
+        tm.stop();
         copy_rows<double>(E, (const double*)Zv, len2, 0, Yout, dim, n1, nvec, len2, 0.0);
         beta2 = 1.0;
     }
@@ -226,6 +257,30 @@ void sigma(adc_ctx* c, const double* X, double* Y, int nvec, int precision) {
         int nz = nvec - z0 < chunk ? nvec - z0 : chunk;
         sigma_block<double>(c, X + (long long)z0 * c->dim, Y + (long long)z0 * c->dim, nz);
     }
+}
+
+// Algorithmic flops of one sigma call (2 per multiply-add) for the contraction
+// sequence above; pp is the particle-particle (EA) / hole-hole (IP) term, whose
+// four-index rebuild is counted once per unique (ac|bd), Naux V^2 (V^2 + 1).
+void sigma_cost(const adc_ctx* c, int nvec, double* total, double* pp) {
+    const double n = nvec, O = c->O, V = c->V, Q = c->Q;
+    double t = 0.0, p = 0.0;
+    if (c->kind == ADC_EA) {
+        t = n * (2 * V * V + 6 * O * V * V * Q + 4 * V * V * Q);
+        if (c->order == 3) {
+            t += n * (18 * O * O * V * V * V + 8 * O * V * V * Q + 2 * V * V * Q +
+                      4 * O * O * O * V * V + 6 * O * O * O * V + 4 * O * V * Q + 6 * O * V * V);
+            p = 2 * n * O * V * V * V * V + Q * V * V * (V * V + 1);
+        }
+    } else {
+        t = n * (2 * O * O + 6 * O * O * V * Q + 4 * O * O * Q);
+        if (c->order == 3) {
+            t += n * (18 * O * O * O * V * V + 14 * O * O * O * V + 6 * O * O * V);
+            p = 2 * n * V * O * O * O * O;
+        }
+    }
+    *total = t + p;
+    *pp = p;
 }
 
 template void sigma_block<double>(adc_ctx*, const double*, double*, int);
