@@ -138,6 +138,7 @@ struct Engine {
     Scratch scratch;
     Ext ext;
     long long gemm_flops = 0;
+    bool bf16 = false;       // FP32 contractions multiply in BF16 (mixed-precision sigma)
     bool timing = false;     // record events around the particle-particle kernels
     double pp_ms = 0.0;      // accumulated milliseconds of those kernels
 };

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "adc_internal.hpp"
+#include "mfma_gemm.hpp"
 
 #include <chrono>
 
@@ -41,9 +42,13 @@ struct adc_ctx {
     adc::DBuf<double> guess;            // warm start
     int nguess = 0;
 
-    // mixed-precision copies (FP32)
-    adc::DBuf<float> fBov, fBvv, fBoo, fovov, foovv, ft;
+    // mixed-precision copies of the sigma operands (FP32; B_vv also as BF16
+    // for the particle-particle rebuild), made on first use
+    adc::DBuf<float> fBoo, fBov, fBvo, fBvv, fM11, fovov, foovv, fooov, foooo, ft, ftt, fgam, fOm,
+        fPi;
+    adc::DBuf<adc::bf16_t> hBvv;
     bool mixed_ready = false;
+    long long pp_slab_bytes = 4LL << 30;   // rebuilt four-index slab (particle-particle term)
 
     // statistics and convergence history of the last solve
     int hist_nroots = 0;
@@ -66,6 +71,10 @@ void setup_adc3(adc_ctx* c, const double* tt, const double* X1);
 // sigma.hip
 template <typename T>
 void sigma_block(adc_ctx* c, const double* X, double* Y, int nvec);
+
+// vvvv.hip: out[x][a][b] = sum_cd (ac|bd) in[x][c][d], (ac|bd) rebuilt from B_vv
+template <typename T, typename TO>
+void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx);
 void sigma(adc_ctx* c, const double* X, double* Y, int nvec, int precision);
 void sigma_cost(const adc_ctx* c, int nvec, double* total, double* pp);
 
@@ -86,8 +95,8 @@ void mul_denom2(Engine& E, const double* t, double* out, const double* eo, const
                 int V);            // out = (e_a + e_b - e_i - e_j) t
 void mul_denom1(Engine& E, const double* s, double* out, const double* eo, const double* ev, int O,
                 int V);            // out = (e_a - e_i) s
-template <typename T>
-void pair_transform(Engine& E, const T* in, long long in_stride, long long in_off, T* out,
+template <typename TI, typename TO>
+void pair_transform(Engine& E, const TI* in, long long in_stride, long long in_off, TO* out,
                     long long out_stride, long long out_off, int nvec, long long nx, int np,
                     double al, double be, double beta_out);
 // out[z][x][p][q] = beta*out + al*in[z][x][p][q] + be*in[z][x][q][p]
@@ -97,8 +106,8 @@ void zeroth_order(Engine& E, const T* Y, T* S, int nvec, long long nx, int np, c
 // S[z][x][p][q] += (sx*ex[x] + sp*(ep[p] + ep[q])) * Y[z][x][p][q]
 void symmetrize_m11(Engine& E, double* M, const double* tau, const double* e, int n, double sgn);
 // M = sgn*diag(e) - 1/2 (tau + tau^T)
-template <typename T>
-void copy_rows(Engine& E, const T* in, long long in_stride, long long in_off, T* out,
+template <typename TI, typename TO>
+void copy_rows(Engine& E, const TI* in, long long in_stride, long long in_off, TO* out,
                long long out_stride, long long out_off, int nvec, long long len, double beta_out);
 void set_diag(Engine& E, double* d, const double* M11, int n1);
 void diag22_adc2(Engine& E, double* d, long long off, long long nx, int np, const double* ex,

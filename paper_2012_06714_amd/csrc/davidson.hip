@@ -14,9 +14,10 @@
 //   already accepted, and dropped if its norm falls below 1e-10;
 //   restart to the current `block` Ritz vectors when V would exceed max_space.
 // Mixed precision ("precision" = 1): sigma runs in reduced precision until the
-// residuals fall below max(sqrt(tol_r), 1e-3); the space is then rebuilt from
-// the Ritz vectors with FP64 sigma and the iteration continues in FP64 to the
-// requested tolerance (iterative refinement of the reduced-precision subspace).
+// residuals fall below max(sqrt(tol_r), 1e-3), or below 3e-3 |theta|, or stop
+// decreasing; the space is then rebuilt from the Ritz vectors with FP64 sigma
+// and the iteration continues in FP64 to the requested tolerance (iterative
+// refinement of the reduced-precision subspace).
 #include "context.hpp"
 
 #include <rocsolver/rocsolver.h>
@@ -136,28 +137,39 @@ struct Dav {
         ADC_HIP(hipStreamSynchronize(E.stream));
     }
 
-    // orthogonalise nd rows of Dm against V[0:m] and against the rows already
-    // accepted (two classical Gram-Schmidt passes per row), drop rows whose norm
-    // falls below 1e-10, normalise the rest; returns the number kept (compacted
-    // to the front of Dm)
+    // orthonormalise nd rows of Dm against V[0:m] and among themselves: the rows
+    // are scaled to unit norm, projected out of V by two block classical
+    // Gram-Schmidt passes (one long-K GEMM each way), then taken one at a time
+    // against the rows already accepted (two passes); rows whose norm falls
+    // below 1e-10 are dropped, the rest normalised and compacted to the front.
+    // Returns the number kept.
     int orthonormalize(double* Dm, int nd, int m) {
-        cmat.alloc((size_t)std::max(1, m + nd), &c->arena);
-        int kept = 0;
+        cmat.alloc((size_t)std::max(1, nd * std::max(m, nd)), &c->arena);
         std::vector<double> nrm;
+        rownorms(Dm, nd, nrm);
+        for (int k = 0; k < nd; ++k) {
+            double s = (nrm[k] > 0 && std::isfinite(nrm[k])) ? 1.0 / nrm[k] : 0.0;
+            hipLaunchKernelGGL(k_scale, dim3(nb_(dim)), dim3(256), 0, E.stream,
+                               Dm + (size_t)k * dim, s, dim);
+        }
+        ADC_HIP(hipGetLastError());
+        if (m > 0) {
+            for (int pass = 0; pass < 2; ++pass) {
+                gemm_rm<double>(E, false, true, nd, m, dim, 1.0, Dm, dim, 0, V.p, dim, 0, 0.0,
+                                cmat.p, m, 0, 1);
+                gemm_rm<double>(E, false, false, nd, dim, m, -1.0, cmat.p, m, 0, V.p, dim, 0, 1.0,
+                                Dm, dim, 0, 1);
+            }
+        }
+        int kept = 0;
         for (int k = 0; k < nd; ++k) {
             double* dk = Dm + (size_t)k * dim;
             double* out = Dm + (size_t)kept * dim;
             if (k != kept)
                 ADC_HIP(hipMemcpyAsync(out, dk, dim * sizeof(double), hipMemcpyDeviceToDevice,
                                        E.stream));
-            for (int pass = 0; pass < 2; ++pass) {
-                if (m > 0) {
-                    gemm_rm<double>(E, false, true, 1, m, dim, 1.0, out, dim, 0, V.p, dim, 0, 0.0,
-                                    cmat.p, m, 0, 1);
-                    gemm_rm<double>(E, false, false, 1, dim, m, -1.0, cmat.p, m, 0, V.p, dim, 0,
-                                    1.0, out, dim, 0, 1);
-                }
-                if (kept > 0) {
+            if (kept > 0) {
+                for (int pass = 0; pass < 2; ++pass) {
                     gemm_rm<double>(E, false, true, 1, kept, dim, 1.0, out, dim, 0, Dm, dim, 0, 0.0,
                                     cmat.p, kept, 0, 1);
                     gemm_rm<double>(E, false, false, 1, dim, kept, -1.0, cmat.p, kept, 0, Dm, dim,
@@ -249,7 +261,13 @@ int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, 
     std::vector<double> theta_old(block, INFINITY), theta(max_space), rnorm;
     int it = 0, status = ADC_OK;
     bool mixed = c->precision == 1;
+    // leave the reduced-precision phase once the residuals reach what BF16
+    // products can resolve: absolutely, relative to the Ritz values, or when
+    // they stop falling (three iterations without halving)
     const double tol_switch = std::max(std::sqrt(tol_r), 1e-3);
+    const double rel_switch = 3e-3;
+    double best_mixed_r = INFINITY;
+    int stall = 0;
     c->st_sigvec = 0;
     c->st_mixed = 0;
     int newstart = 0;    // first basis vector without a sigma vector
@@ -335,7 +353,14 @@ int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, 
             for (int k = 0; k < nbk; ++k) fprintf(stderr, " %.10f(%.1e)", theta[k], rnorm[k]);
             fprintf(stderr, "\n");
         }
-        if (mixed && maxr <= tol_switch) {
+        double rel_r = 0.0;
+        for (int k = 0; k < nroots; ++k)
+            rel_r = std::max(rel_r, rnorm[k] / std::max(1.0, std::fabs(theta[k])));
+        if (mixed) {
+            stall = (maxr > 0.5 * best_mixed_r) ? stall + 1 : 0;
+            best_mixed_r = std::min(best_mixed_r, maxr);
+        }
+        if (mixed && (maxr <= tol_switch || rel_r <= rel_switch || stall >= 3)) {
             // FP64 refinement: rebuild the space from the Ritz vectors with FP64 sigma
             mixed = false;
             ADC_HIP(hipMemcpyAsync(d.V.p, d.X.p, (size_t)nbk * dim * sizeof(double),

@@ -119,23 +119,23 @@ void mul_denom1(Engine& E, const double* s, double* out, const double* eo, const
 // one 32x32 (p,q) tile per block; the (q,p) tile is read through LDS so that
 // both global reads and the write are coalesced.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void k_pair(const T* __restrict__ in, long long in_stride, long long in_off,
-                       T* __restrict__ out, long long out_stride, long long out_off, long long nzx,
+template <typename TI, typename TO>
+__global__ void k_pair(const TI* __restrict__ in, long long in_stride, long long in_off,
+                       TO* __restrict__ out, long long out_stride, long long out_off, long long nzx,
                        long long nx, int np, double al, double be, double beta) {
-    __shared__ T tt[32][33];
+    __shared__ TI tt[32][33];
     const int tilesq = (np + 31) / 32;
     const int tp = blockIdx.x / tilesq, tq = blockIdx.x - tp * tilesq;
     const int tx = threadIdx.x, ty = threadIdx.y;
     const long long npp = (long long)np * np;
     for (long long zx = blockIdx.y; zx < nzx; zx += gridDim.y) {
         long long z = zx / nx, x = zx - z * nx;
-        const T* src = in + z * in_stride + in_off + x * npp;
-        T* dst = out + z * out_stride + out_off + x * npp;
+        const TI* src = in + z * in_stride + in_off + x * npp;
+        TO* dst = out + z * out_stride + out_off + x * npp;
         // load transposed tile: elements [q][p] for q in tile tq, p in tile tp
         for (int k = ty; k < 32; k += 8) {
             int q = tq * 32 + k, p = tp * 32 + tx;
-            tt[k][tx] = (q < np && p < np) ? src[(long long)q * np + p] : T(0);
+            tt[k][tx] = (q < np && p < np) ? src[(long long)q * np + p] : TI(0);
         }
         __syncthreads();
         for (int k = ty; k < 32; k += 8) {
@@ -144,23 +144,23 @@ __global__ void k_pair(const T* __restrict__ in, long long in_stride, long long 
                 long long o = (long long)p * np + q;
                 double v = al * (double)src[o] + be * (double)tt[tx][k];
                 if (beta != 0.0) v += beta * (double)dst[o];
-                dst[o] = (T)v;
+                dst[o] = (TO)v;
             }
         }
         __syncthreads();
     }
 }
 
-template <typename T>
-void pair_transform(Engine& E, const T* in, long long in_stride, long long in_off, T* out,
+template <typename TI, typename TO>
+void pair_transform(Engine& E, const TI* in, long long in_stride, long long in_off, TO* out,
                     long long out_stride, long long out_off, int nvec, long long nx, int np,
                     double al, double be, double beta_out) {
     if (nvec == 0 || nx == 0 || np == 0) return;
     int tiles = (np + 31) / 32;
     long long nzx = (long long)nvec * nx;
     unsigned gy = (unsigned)(nzx < 65535 ? nzx : 65535);
-    hipLaunchKernelGGL(k_pair<T>, dim3(tiles * tiles, gy), dim3(32, 8), 0, E.stream, in, in_stride,
-                       in_off, out, out_stride, out_off, nzx, nx, np, al, be, beta_out);
+    hipLaunchKernelGGL((k_pair<TI, TO>), dim3(tiles * tiles, gy), dim3(32, 8), 0, E.stream, in,
+                       in_stride, in_off, out, out_stride, out_off, nzx, nx, np, al, be, beta_out);
     ADC_HIP(hipGetLastError());
 }
 
@@ -242,44 +242,46 @@ void set_diag(Engine& E, double* d, const double* M11, int n1) {
     ADC_HIP(hipGetLastError());
 }
 
-template <typename T>
-__global__ void k_copy_rows(const T* __restrict__ in, long long in_stride, long long in_off,
-                            T* __restrict__ out, long long out_stride, long long out_off, int nvec,
+template <typename TI, typename TO>
+__global__ void k_copy_rows(const TI* __restrict__ in, long long in_stride, long long in_off,
+                            TO* __restrict__ out, long long out_stride, long long out_off, int nvec,
                             long long len, double beta) {
     long long total = (long long)nvec * len;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
         long long z = e / len, k = e - z * len;
-        T* o = out + z * out_stride + out_off + k;
+        TO* o = out + z * out_stride + out_off + k;
         double v = (double)in[z * in_stride + in_off + k];
         if (beta != 0.0) v += beta * (double)*o;
-        *o = (T)v;
+        *o = (TO)v;
     }
 }
 
-template <typename T>
-void copy_rows(Engine& E, const T* in, long long in_stride, long long in_off, T* out,
+template <typename TI, typename TO>
+void copy_rows(Engine& E, const TI* in, long long in_stride, long long in_off, TO* out,
                long long out_stride, long long out_off, int nvec, long long len, double beta_out) {
     long long total = (long long)nvec * len;
     if (!total) return;
-    hipLaunchKernelGGL(k_copy_rows<T>, dim3(nblk(total, 256)), dim3(256), 0, E.stream, in,
+    hipLaunchKernelGGL((k_copy_rows<TI, TO>), dim3(nblk(total, 256)), dim3(256), 0, E.stream, in,
                        in_stride, in_off, out, out_stride, out_off, nvec, len, beta_out);
     ADC_HIP(hipGetLastError());
 }
 
-template void pair_transform<double>(Engine&, const double*, long long, long long, double*,
-                                     long long, long long, int, long long, int, double, double,
-                                     double);
-template void pair_transform<float>(Engine&, const float*, long long, long long, float*, long long,
-                                    long long, int, long long, int, double, double, double);
+#define ADC_PAIR_INST(TI, TO)                                                                  \
+    template void pair_transform<TI, TO>(Engine&, const TI*, long long, long long, TO*, long long, \
+                                         long long, int, long long, int, double, double, double); \
+    template void copy_rows<TI, TO>(Engine&, const TI*, long long, long long, TO*, long long,      \
+                                    long long, int, long long, double);
+ADC_PAIR_INST(double, double)
+ADC_PAIR_INST(float, float)
+ADC_PAIR_INST(double, float)
+ADC_PAIR_INST(float, double)
+ADC_PAIR_INST(double, bf16_t)
+#undef ADC_PAIR_INST
 template void zeroth_order<double>(Engine&, const double*, double*, int, long long, int,
                                    const double*, const double*, double, double);
 template void zeroth_order<float>(Engine&, const float*, float*, int, long long, int,
                                   const double*, const double*, double, double);
-template void copy_rows<double>(Engine&, const double*, long long, long long, double*, long long,
-                                long long, int, long long, double);
-template void copy_rows<float>(Engine&, const float*, long long, long long, float*, long long,
-                               long long, int, long long, double);
 
 }  // namespace adc
 

@@ -1,0 +1,51 @@
+// Matrix-core GEMM (mfma_gemm.hip): row-major, strided batches, permuted output.
+#pragma once
+
+#include "adc_internal.hpp"
+
+namespace adc {
+
+using bf16_t = __bf16;
+
+// accumulation / scaling type of each input type
+template <typename T> struct AccOf { using type = T; };
+template <> struct AccOf<bf16_t> { using type = float; };
+
+// Output index map.  Row m = m1*rsplit + m2, column n = n1*csplit + n2:
+//   offset = m1*rs1 + m2*rs2 + n1*cs1 + n2*cs2 + batch*sC
+// The plain row-major store with leading dimension ldc is
+//   rsplit = csplit = 0 (no split), rs2 = ldc, cs2 = 1.
+struct GemmOut {
+    long long rsplit = 0, rs1 = 0, rs2 = 0;
+    long long csplit = 0, cs1 = 0, cs2 = 1;
+    long long sC = 0;
+    static GemmOut rowmajor(long long ldc, long long sC = 0) {
+        GemmOut o;
+        o.rs2 = ldc;
+        o.sC = sC;
+        return o;
+    }
+};
+
+struct GemmShape {
+    long long M, N, K, lda, ldb, sA, sB, sC;
+    long long rsplit, rs1, rs2, csplit, cs1, cs2;
+    bool vecA, vecB;
+};
+
+// C = alpha op(A) op(B) + beta C on stream st.
+//   ta = false: A is [M][K] (lda >= K);  ta = true: A is [K][M] (lda >= M)
+//   tb = true:  B is [N][K] (ldb >= K);  tb = false: B is [K][N] (ldb >= N)
+// Operands stored as TI, multiplied as T on the matrix cores (TI = FP32 with
+// T = BF16 rounds while staging), accumulated in AccOf<T>, written as TO.
+// Instantiated for (TI, T, TO) = (f64, f64, f64), (f32, f32, f32),
+// (f32, bf16, f32), (bf16, bf16, f32), (bf16, bf16, bf16).
+template <typename TI, typename T, typename TO>
+void mfma_gemm(hipStream_t st, bool ta, bool tb, long long M, long long N, long long K,
+               typename AccOf<T>::type alpha, const TI* A, long long lda, long long sA, const TI* B,
+               long long ldb, long long sB, typename AccOf<T>::type beta, TO* C, GemmOut out,
+               long long batch, int kind = 0);
+// kind only names the kernel in profiles: 0 plain, 1 four-index rebuild,
+// 2 particle-particle contraction (1 and 2 are NT only)
+
+}  // namespace adc

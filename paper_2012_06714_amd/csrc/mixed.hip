@@ -1,0 +1,57 @@
+// Reduced-precision copies of the resident sigma operands, made on the first
+// mixed-precision sigma call: FP32 for every tensor the contractions read
+// (their GEMMs round to BF16 while staging tiles and accumulate in FP32) and
+// BF16 for B_vv, the operand of the particle-particle rebuild.  The FP64
+// originals stay resident for the refinement passes.
+#include "context.hpp"
+
+namespace adc {
+
+template <typename TO>
+__global__ void k_narrow(const double* __restrict__ in, TO* __restrict__ out, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        out[i] = (TO)in[i];
+}
+
+template <typename TO>
+static void narrow(adc_ctx* c, const DBuf<double>& src, DBuf<TO>& dst) {
+    if (!src.p || src.n == 0) {
+        dst.release();
+        return;
+    }
+    dst.alloc(src.n, &c->arena);
+    size_t g = (src.n + 255) / 256;
+    if (g > (1u << 20)) g = 1u << 20;
+    hipLaunchKernelGGL(k_narrow<TO>, dim3((unsigned)g), dim3(256), 0, c->E.stream, src.p, dst.p,
+                       src.n);
+    ADC_HIP(hipGetLastError());
+}
+
+void build_mixed(adc_ctx* c) {
+    if (c->mixed_ready) return;
+    narrow(c, c->Boo, c->fBoo);
+    narrow(c, c->Bov, c->fBov);
+    narrow(c, c->Bvo, c->fBvo);
+    narrow(c, c->M11, c->fM11);
+    if (c->order == 3) {
+        narrow(c, c->ovov, c->fovov);
+        narrow(c, c->oovv, c->foovv);
+        narrow(c, c->ooov, c->fooov);
+        narrow(c, c->t, c->ft);
+        narrow(c, c->tt, c->ftt);
+        narrow(c, c->gam, c->fgam);
+        if (c->kind == ADC_EA) {
+            narrow(c, c->Bvv, c->hBvv);
+        } else {
+            narrow(c, c->oooo, c->foooo);
+            narrow(c, c->Om, c->fOm);
+            narrow(c, c->Pi, c->fPi);
+        }
+    }
+    // the first-order coupling reads B_vv in both kinds (EA: (ac|Q) products)
+    if (c->kind == ADC_EA) narrow(c, c->Bvv, c->fBvv);
+    c->mixed_ready = true;
+}
+
+}  // namespace adc

@@ -13,8 +13,6 @@
 
 namespace adc {
 
-template <typename T>
-void vvvv_reference(adc_ctx* c, const T* Bvv, const T* in, T* out, long long nx, T beta);
 
 namespace {
 struct Buf {
@@ -185,7 +183,7 @@ void setup_adc3(adc_ctx* c, const double* tt, const double* X1) {
     // ---- particle-particle ladder and second-order doubles --------------------------
     Buf Lb, Ltb;
     double* Lam = Lb.get(c, OO * VV);
-    vvvv_reference<double>(c, Bvv, t, Lam, (long long)OO, 0.0);   // Lambda_ij^ab = (ac|bd) t_ij^cd
+    vvvv_apply<double, double>(c, Bvv, t, Lam, (long long)OO);   // Lambda_ij^ab = (ac|bd) t_ij^cd
     c->u.alloc(OO * VV, &c->arena);
     double* u = c->u.p;
     ctr<double>(E, 1.0, "klba", t, "likj", oooo, 0.0, "ijab", u);

@@ -135,7 +135,7 @@ static void sigma_adc3_ea_terms(adc_ctx* c, const Views<T>& v, const T* Y1, cons
     ctr<T>(E, T(1), "zakd", X1, "ikbd", v.t, T(1), "ziab", S2);
     ctr<T>(E, T(1), "zbkd", X1, "ikda", v.t, T(1), "ziab", S2);
     // first-order 2p1h-2p1h: (2 Y_acj - Y_caj)(jc|ib) - Y_acj (ji|bc) - Y_cbj (ji|ac)
-    pair_transform<T>(E, Y2, (long long)(O * V * V), 0, X1, (long long)(O * V * V), 0, nvec, O,
+    pair_transform<T, T>(E, Y2, (long long)(O * V * V), 0, X1, (long long)(O * V * V), 0, nvec, O,
                       (int)V, 2.0, -1.0, 0.0);
     ctr<T>(E, T(1), "zjac", X1, "jcib", v.ovov, T(1), "ziab", S2);
     ctr<T>(E, T(-1), "zjac", Y2, "jibc", v.oovv, T(1), "ziab", S2);
@@ -174,15 +174,12 @@ static void sigma_adc3_ip_terms(adc_ctx* c, const Views<T>& v, const T* Y1, cons
     ctr<T>(E, T(1), "zjlb", X1, "ilba", v.t, T(1), "zaij", S2);
     ctr<T>(E, T(-1), "zk", Y1, "kjia", v.Pi, T(1), "zaij", S2);
     // first-order 2h1p-2h1p: (2 Y_ikb - Y_kib)(kb|ja) - Y_ikb (kj|ab) - Y_kjb (ki|ab)
-    pair_transform<T>(E, Y2, (long long)(V * O * O), 0, X2, (long long)(V * O * O), 0, nvec, V,
+    pair_transform<T, T>(E, Y2, (long long)(V * O * O), 0, X2, (long long)(V * O * O), 0, nvec, V,
                       (int)O, 2.0, -1.0, 0.0);
     ctr<T>(E, T(1), "zbik", X2, "kbja", v.ovov, T(1), "zaij", S2);
     ctr<T>(E, T(-1), "zbik", Y2, "kjab", v.oovv, T(1), "zaij", S2);
     ctr<T>(E, T(-1), "zbkj", Y2, "kiab", v.oovv, T(1), "zaij", S2);
 }
-
-template <typename T>
-void vvvv_reference(adc_ctx* c, const T* Bvv, const T* in, T* out, long long nx, T beta);
 
 template <typename T>
 static Views<T> views(adc_ctx* c);
@@ -194,6 +191,18 @@ Views<double> views<double>(adc_ctx* c) {
                          c->tt.p,   c->gam.p,  c->Om.p,   c->Pi.p};
 }
 
+template <>
+Views<float> views<float>(adc_ctx* c) {
+    build_mixed(c);
+    return Views<float>{c->fBoo.p,  c->fBov.p,  c->fBvo.p,  c->fBvv.p, c->fM11.p,
+                        c->fovov.p, c->foovv.p, c->fooov.p, c->foooo.p, c->ft.p,
+                        c->ftt.p,   c->fgam.p,  c->fOm.p,   c->fPi.p};
+}
+
+// compute type of the particle-particle GEMMs: FP64, or BF16 in the mixed mode
+template <typename T> struct PPType { using type = double; };
+template <> struct PPType<float> { using type = bf16_t; };
+
 template <typename T>
 void sigma_block(adc_ctx* c, const double* X, double* Yout, int nvec) {
     Engine& E = c->E;
@@ -204,6 +213,13 @@ void sigma_block(adc_ctx* c, const double* X, double* Yout, int nvec) {
     const long long len2 = nx * np * np;
     const long long dim = c->dim;
     Views<T> v = views<T>(c);
+    // FP32 contractions multiply in BF16 on the matrix cores in the mixed mode
+    struct Bf16Scope {
+        Engine& e;
+        bool old;
+        Bf16Scope(Engine& en, bool on) : e(en), old(en.bf16) { e.bf16 = on; }
+        ~Bf16Scope() { e.bf16 = old; }
+    } scope(E, sizeof(T) == 4);
 
     T* Y1 = slot<T>(E, S_Y1, (size_t)nvec * n1);
     T* Y2 = slot<T>(E, S_Y2, (size_t)nvec * len2);
@@ -211,8 +227,8 @@ void sigma_block(adc_ctx* c, const double* X, double* Yout, int nvec) {
     T* S2 = slot<T>(E, S_S2, (size_t)nvec * len2);
 
     // Y = S^{-1/2} Z
-    copy_rows<double>(E, X, dim, 0, (double*)Y1, n1, 0, nvec, n1, 0.0);
-    pair_transform<double>(E, X, dim, n1, (double*)Y2, len2, 0, nvec, nx, np, ALI, BEI, 0.0);
+    copy_rows<double, T>(E, X, dim, 0, Y1, n1, 0, nvec, n1, 0.0);
+    pair_transform<double, T>(E, X, dim, n1, Y2, len2, 0, nvec, nx, np, ALI, BEI, 0.0);
 
     sigma_adc2_terms<T>(c, v, Y1, Y2, S1, S2, nvec);
     const bool ea3 = c->order == 3 && c->kind == ADC_EA;
@@ -222,40 +238,45 @@ void sigma_block(adc_ctx* c, const double* X, double* Yout, int nvec) {
 
     // Z-basis result: S^{1/2} sigma_Y (+ the particle-particle term, which commutes
     // with the pair metric and acts on Z directly)
-    copy_rows<double>(E, (const double*)S1, n1, 0, Yout, dim, 0, nvec, n1, 0.0);
+    copy_rows<T, double>(E, S1, n1, 0, Yout, dim, 0, nvec, n1, 0.0);
     double beta2 = 0.0;
     if (ea3) {
-        T* Zp = slot<T>(E, S_T4, (size_t)nvec * len2);
+        using P = typename PPType<T>::type;
+        const P* Bvv = sizeof(T) == 8 ? (const P*)c->Bvv.p : (const P*)c->hBvv.p;
+        P* Zp = slot<P>(E, S_T4, (size_t)nvec * len2);
         T* Zv = slot<T>(E, S_T1, (size_t)nvec * len2);
-        copy_rows<double>(E, X, dim, n1, (double*)Zp, len2, 0, nvec, len2, 0.0);
+        copy_rows<double, P>(E, X, dim, n1, Zp, len2, 0, nvec, len2, 0.0);
         PPTimer tm(E);
-        vvvv_reference<T>(c, v.Bvv, Zp, Zv, (long long)nvec * c->O, T(0));
+        vvvv_apply<P, T>(c, Bvv, Zp, Zv, (long long)nvec * c->O);
         tm.stop();
-        copy_rows<double>(E, (const double*)Zv, len2, 0, Yout, dim, n1, nvec, len2, 0.0);
+        copy_rows<T, double>(E, Zv, len2, 0, Yout, dim, n1, nvec, len2, 0.0);
         beta2 = 1.0;
     }
     if (ip3) {
         // hole-hole term sum_kl (ki|lj) Z_kla, commutes with the pair metric
         T* Zp = slot<T>(E, S_T4, (size_t)nvec * len2);
         T* Zv = slot<T>(E, S_T1, (size_t)nvec * len2);
-        copy_rows<double>(E, X, dim, n1, (double*)Zp, len2, 0, nvec, len2, 0.0);
+        copy_rows<double, T>(E, X, dim, n1, Zp, len2, 0, nvec, len2, 0.0);
         PPTimer tm(E);
         ctr<T>(E, T(1), "kilj", v.oooo, "zakl", Zp, T(0), "zaij", Zv);
         tm.stop();
-        copy_rows<double>(E, (const double*)Zv, len2, 0, Yout, dim, n1, nvec, len2, 0.0);
+        copy_rows<T, double>(E, Zv, len2, 0, Yout, dim, n1, nvec, len2, 0.0);
         beta2 = 1.0;
     }
-    pair_transform<double>(E, (const double*)S2, len2, 0, Yout, dim, n1, nvec, nx, np, AL, BE,
-                           beta2);
+    pair_transform<T, double>(E, S2, len2, 0, Yout, dim, n1, nvec, nx, np, AL, BE, beta2);
 }
 
 void sigma(adc_ctx* c, const double* X, double* Y, int nvec, int precision) {
-    (void)precision;
     // process in chunks to bound the scratch footprint
     const int chunk = 64;
     for (int z0 = 0; z0 < nvec; z0 += chunk) {
         int nz = nvec - z0 < chunk ? nvec - z0 : chunk;
-        sigma_block<double>(c, X + (long long)z0 * c->dim, Y + (long long)z0 * c->dim, nz);
+        const double* Xz = X + (long long)z0 * c->dim;
+        double* Yz = Y + (long long)z0 * c->dim;
+        if (precision == 1)
+            sigma_block<float>(c, Xz, Yz, nz);
+        else
+            sigma_block<double>(c, Xz, Yz, nz);
     }
 }
 
@@ -284,5 +305,6 @@ void sigma_cost(const adc_ctx* c, int nvec, double* total, double* pp) {
 }
 
 template void sigma_block<double>(adc_ctx*, const double*, double*, int);
+template void sigma_block<float>(adc_ctx*, const double*, double*, int);
 
 }  // namespace adc

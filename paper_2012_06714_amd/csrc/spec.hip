@@ -19,8 +19,8 @@ void spec_amplitudes(adc_ctx* c, const double* vecs, int nvec, double* Xout) {
     y2.alloc((size_t)nvec * len2, &c->arena);
     xo.alloc((size_t)nvec * O, &c->arena);
     xv.alloc((size_t)nvec * V, &c->arena);
-    copy_rows<double>(E, vecs, dim, 0, y1.p, n1, 0, nvec, n1, 0.0);
-    pair_transform<double>(E, vecs, dim, n1, y2.p, len2, 0, nvec, nx, np, ALI, BEI, 0.0);
+    copy_rows<double, double>(E, vecs, dim, 0, y1.p, n1, 0, nvec, n1, 0.0);
+    pair_transform<double, double>(E, vecs, dim, n1, y2.p, len2, 0, nvec, nx, np, ALI, BEI, 0.0);
     const double* t = c->t.p;
     if (c->kind == ADC_EA) {
         // occupied p = k: sum_bcj Y_bcj t~_jk^cb - sum_c Y_c s_kc        (order 2)
@@ -34,11 +34,11 @@ void spec_amplitudes(adc_ctx* c, const double* vecs, int nvec, double* Xout) {
             ctr<double>(E, -1.0, "zc", y1.p, "kc", c->s.p, 1.0, "zk", xo.p);
         }
         // virtual p = c: Y_c + sum_e rho_ce Y_e
-        copy_rows<double>(E, y1.p, V, 0, xv.p, V, 0, nvec, V, 0.0);
+        copy_rows<double, double>(E, y1.p, V, 0, xv.p, V, 0, nvec, V, 0.0);
         ctr<double>(E, 1.0, "ce", c->rho.p, "ze", y1.p, 1.0, "zc", xv.p);
     } else {
         // occupied m: Y_m + sum_j rho_jm Y_j
-        copy_rows<double>(E, y1.p, O, 0, xo.p, O, 0, nvec, O, 0.0);
+        copy_rows<double, double>(E, y1.p, O, 0, xo.p, O, 0, nvec, O, 0.0);
         ctr<double>(E, 1.0, "jm", c->rho.p, "zj", y1.p, 1.0, "zm", xo.p);
         // virtual e: sum_jkb Y_jkb t~_kj^be + sum_j Y_j s_je              (order 2)
         //            sum_jkb Y_jkb (t~ + u~)_kj^be + sum_j Y_j omega_je     (order 3)
@@ -51,8 +51,8 @@ void spec_amplitudes(adc_ctx* c, const double* vecs, int nvec, double* Xout) {
             ctr<double>(E, 1.0, "zj", y1.p, "je", c->s.p, 1.0, "ze", xv.p);
         }
     }
-    copy_rows<double>(E, xo.p, O, 0, Xout, N, 0, nvec, O, 0.0);
-    copy_rows<double>(E, xv.p, V, 0, Xout, N, O, nvec, V, 0.0);
+    copy_rows<double, double>(E, xo.p, O, 0, Xout, N, 0, nvec, O, 0.0);
+    copy_rows<double, double>(E, xv.p, V, 0, Xout, N, O, nvec, V, 0.0);
     ADC_HIP(hipStreamSynchronize(E.stream));
 }
 

@@ -1,6 +1,7 @@
-// Tensor helpers: permutation kernel, row-major GEMM wrapper over rocBLAS and
+// Tensor helpers: permutation kernel, row-major GEMM on the matrix-core kernel and
 // an einsum-style binary contraction that maps onto (strided, batched) GEMM.
 #include "adc_internal.hpp"
+#include "mfma_gemm.hpp"
 
 #include <algorithm>
 #include <cstring>
@@ -79,6 +80,57 @@ void permute(Engine& E, T alpha, const char* si, const T* in, T beta, const char
 // ---------------------------------------------------------------------------
 // GEMM (row-major view over column-major rocBLAS)
 // ---------------------------------------------------------------------------
+// Skinny products with a long summed index (Davidson overlaps, gemv-like
+// contractions) would leave most of the chip idle: split K into chunks run as
+// one batched GEMM into partial results, then reduce them in a fixed order.
+template <typename A>
+__global__ void k_splitk_reduce(const A* __restrict__ part, int S, long long M, long long N,
+                                A* __restrict__ C, long long ldc, A beta) {
+    const long long MN = M * N;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < MN;
+         e += (long long)gridDim.x * blockDim.x) {
+        A v = 0;
+        for (int s = 0; s < S; ++s) v += part[s * MN + e];
+        const long long m = e / N, n = e - m * N;
+        A* o = C + m * ldc + n;
+        *o = (beta == A(0)) ? v : beta * *o + v;
+    }
+}
+
+template <typename TI, typename T>
+static void gemm_any(Engine& E, bool ta, bool tb, long long M, long long N, long long K, TI alpha,
+                     const TI* A, long long lda, long long sA, const TI* B, long long ldb,
+                     long long sB, TI beta, TI* C, long long ldc, long long sC, long long batch) {
+    using Acc = typename AccOf<T>::type;
+    static_assert(sizeof(Acc) == sizeof(TI), "accumulator must match the output type");
+    const long long tiles = ((M + 63) / 64) * ((N + 63) / 64) * batch;
+    if (batch == 1 && tiles < 64 && K >= 16384) {
+        long long S = std::min<long long>(K / 8192, 512 / tiles);
+        if (S >= 2) {
+            long long Kc = (K + S - 1) / S;
+            Kc = (Kc + 63) / 64 * 64;
+            S = (K + Kc - 1) / Kc;
+            const long long Klast = K - (S - 1) * Kc;
+            Acc* part = (Acc*)E.scratch.get(31, sizeof(Acc) * S * M * N);
+            const long long offA = ta ? Kc * lda : Kc, offB = tb ? Kc : Kc * ldb;
+            if (S > 1)
+                mfma_gemm<TI, T, Acc>(E.stream, ta, tb, M, N, Kc, (Acc)alpha, A, lda, offA, B,
+                                      ldb, offB, Acc(0), part, GemmOut::rowmajor(N, M * N), S - 1);
+            mfma_gemm<TI, T, Acc>(E.stream, ta, tb, M, N, Klast, (Acc)alpha, A + (S - 1) * offA,
+                                  lda, 0, B + (S - 1) * offB, ldb, 0, Acc(0),
+                                  part + (S - 1) * M * N, GemmOut::rowmajor(N), 1);
+            long long g = (M * N + 255) / 256;
+            if (g > 4096) g = 4096;
+            hipLaunchKernelGGL(k_splitk_reduce<Acc>, dim3((unsigned)g), dim3(256), 0, E.stream,
+                               part, (int)S, M, N, (Acc*)C, ldc, (Acc)beta);
+            ADC_HIP(hipGetLastError());
+            return;
+        }
+    }
+    mfma_gemm<TI, T, TI>(E.stream, ta, tb, M, N, K, (Acc)alpha, A, lda, sA, B, ldb, sB, (Acc)beta, C,
+                         GemmOut::rowmajor(ldc, sC), batch);
+}
+
 template <>
 void gemm_rm<double>(Engine& E, bool ta, bool tb, long long M, long long N, long long K, double alpha,
                      const double* A, long long lda, long long sA, const double* B, long long ldb,
@@ -86,11 +138,8 @@ void gemm_rm<double>(Engine& E, bool ta, bool tb, long long M, long long N, long
                      long long batch) {
     if (M == 0 || N == 0 || batch == 0) return;
     E.gemm_flops += 2LL * M * N * K * batch;
-    // row-major C = op(A) op(B)  <=>  col-major C^T = op(B)^T op(A)^T
-    ADC_BLAS(rocblas_dgemm_strided_batched_64(
-        E.blas, tb ? rocblas_operation_transpose : rocblas_operation_none,
-        ta ? rocblas_operation_transpose : rocblas_operation_none, N, M, K, &alpha, B, ldb, sB, A,
-        lda, sA, &beta, C, ldc, sC, batch));
+    gemm_any<double, double>(E, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC,
+                             batch);
 }
 
 template <>
@@ -100,10 +149,12 @@ void gemm_rm<float>(Engine& E, bool ta, bool tb, long long M, long long N, long 
                     long long batch) {
     if (M == 0 || N == 0 || batch == 0) return;
     E.gemm_flops += 2LL * M * N * K * batch;
-    ADC_BLAS(rocblas_sgemm_strided_batched_64(
-        E.blas, tb ? rocblas_operation_transpose : rocblas_operation_none,
-        ta ? rocblas_operation_transpose : rocblas_operation_none, N, M, K, &alpha, B, ldb, sB, A,
-        lda, sA, &beta, C, ldc, sC, batch));
+    if (E.bf16)
+        gemm_any<float, bf16_t>(E, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc,
+                                sC, batch);
+    else
+        gemm_any<float, float>(E, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC,
+                               batch);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,40 +1,51 @@
-// The first-order particle-particle term rebuilt from the DF factors:
-//   out[x][a][b] = beta*out + sum_cd (ac|bd) in[x][c][d],   (ac|bd) = sum_Q B^Q_ac B^Q_bd
-// used for the 2p1h-2p1h block of EA sigma (x = vector, occupied index) and for
-// the particle-particle ladder of the second-order doubles (x = ij).  The
-// four-index block is never stored whole (V^4 words); this routine rebuilds
-// it for a block of a values at a time.
+// The particle-particle term rebuilt from the density-fitted factors (the
+// four-virtual integrals are never stored whole, Sec. III.C):
+//   out[x][a][b] = sum_cd (ac|bd) in[x][c][d],   (ac|bd) = sum_Q B^Q_ac B^Q_bd.
+// It is the 2p1h-2p1h first-order ladder of EA sigma (x = vector, occupied
+// index) and the particle-particle ladder of the second-order doubles (x = ij).
 //
-// Reference path (rocBLAS): for each a-block A,
-//   K[a][c][d][b] = sum_Q Bvv[a][c][Q] Bvv[d][b][Q]     (Bvv symmetric in its pair)
-//   out[x][a][b] += sum_(cd) in[x][(cd)] K[a][(cd)][b]   (one GEMM per a, batched)
+// For a block of a values the rebuild is one matrix-core GEMM over Q,
+//   rows (a, c) of B_vv  x  rows (b, d) of B_vv,
+// whose epilogue scatters the result into the slab K[a][b][c][d]; the
+// contraction is then a second GEMM, out[x][(a,b)] = in[x][(c,d)] K[(a,b)][(c,d)],
+// with both operands contiguous in the summed pair (c, d).  The slab is the
+// only V^3-sized buffer; its size bounds the a-block.
 #include "context.hpp"
 
 #include <algorithm>
 
 namespace adc {
 
-template <typename T>
-void vvvv_reference(adc_ctx* c, const T* Bvv, const T* in, T* out, long long nx, T beta) {
+template <typename T, typename TO>
+void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx) {
     Engine& E = c->E;
-    const long long V = c->V, Q = c->Q, VV = V * V;
-    // a-block size: keep the rebuilt slab near 1 GiB
-    long long ta = std::max<long long>(1, (1LL << 30) / (long long)(sizeof(T) * VV * V));
-    ta = std::min(ta, V);
-    T* K = (T*)E.scratch.get(30, sizeof(T) * ta * VV * V);
+    const long long V = c->V, Q = c->Q, VV = V * V, V3 = VV * V;
+    if (nx <= 0) return;
+    long long ta_max = std::max<long long>(1, c->pp_slab_bytes / (long long)(sizeof(T) * V3));
+    ta_max = std::min(ta_max, V);
+    const long long nblk = (V + ta_max - 1) / ta_max;
+    const long long ta = (V + nblk - 1) / nblk;            // balanced a-blocks
+    T* K = (T*)E.scratch.get(30, sizeof(T) * ta * V3);
+    GemmOut slab;                                          // (a, c) x (b, d) -> [a][b][c][d]
+    slab.rsplit = V;
+    slab.rs1 = V3;
+    slab.rs2 = V;
+    slab.csplit = V;
+    slab.cs1 = VV;
+    slab.cs2 = 1;
+    using A = typename AccOf<T>::type;
     for (long long a0 = 0; a0 < V; a0 += ta) {
-        long long na = std::min(ta, V - a0);
-        // K[(a,c)][(d,b)] = Bvv[(a,c)][Q] . Bvv[(d,b)][Q]^T
-        gemm_rm<T>(E, false, true, na * V, VV, Q, T(1), Bvv + a0 * V * Q, Q, 0, Bvv, Q, 0, T(0), K,
-                   VV, 0, 1);
-        // out[x][a][b] for a in block: batch over a, C stride V, ldc V^2
-        gemm_rm<T>(E, false, false, nx, V, VV, T(1), in, VV, 0, K, V, VV * V, beta, out + a0 * V,
-                   VV, V, na);
+        const long long na = std::min(ta, V - a0);
+        mfma_gemm<T, T, T>(E.stream, false, true, na * V, VV, Q, A(1), Bvv + a0 * V * Q, Q, 0, Bvv,
+                           Q, 0, A(0), K, slab, 1, 1);
+        mfma_gemm<T, T, TO>(E.stream, false, true, nx, na * V, VV, A(1), in, VV, 0, K, VV, 0, A(0),
+                            out + a0 * V, GemmOut::rowmajor(VV), 1, 2);
+        E.gemm_flops += 2LL * na * V * VV * Q + 2LL * nx * na * V * VV;
     }
 }
 
-template void vvvv_reference<double>(adc_ctx*, const double*, const double*, double*, long long,
-                                     double);
-template void vvvv_reference<float>(adc_ctx*, const float*, const float*, float*, long long, float);
+template void vvvv_apply<double, double>(adc_ctx*, const double*, const double*, double*,
+                                         long long);
+template void vvvv_apply<bf16_t, float>(adc_ctx*, const bf16_t*, const bf16_t*, float*, long long);
 
 }  // namespace adc
