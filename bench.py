@@ -57,6 +57,7 @@ def main():
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
     ap.add_argument("--no-davidson", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tune-log", action="store_true", help="log the GEMM autotuner's choices")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -83,6 +84,8 @@ def main():
     t_setup = time.perf_counter() - t0
     del Bd
     log(f"bench: setup {t_setup:.2f} s, dim {ctx.dim}")
+    if args.tune_log:
+        ctx.set_option("autotune", 2)
 
     nvec = wl.block
     X = torch.tensor(random_vectors(ctx.dim, nvec, 11), device=dev)
@@ -109,8 +112,8 @@ def main():
     def solve(prec, e_ref=None):
         ctx.set_option("precision", 1 if prec == "mixed" else 0)
         ctx.set_option("block", wl.block)
-        ctx.set_option("tol_e", 1e-10)
-        ctx.set_option("tol_r", 1e-5)
+        ctx.set_option("tol_e", 1e-7)
+        ctx.set_option("tol_r", 1e-7)
         ctx.set_option("max_iter", 400)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -122,6 +125,10 @@ def main():
         err = np.max(np.abs(th - ref[None, :]), axis=1)
         hit = np.nonzero(err <= 1e-6)[0]
         t_1e6 = float(tsec[hit[0]]) if hit.size else None
+        scaled_r = np.max(rn / np.maximum(1.0, np.abs(th)), axis=1)
+        for k in range(0, len(tsec), max(1, len(tsec) // 25)):
+            log(f"  {prec} it {k + 1:4d} t {tsec[k]:7.3f} s  max|theta-ref| {err[k]:.3e}  "
+                f"max r/max(1,|theta|) {scaled_r[k]:.3e}  {'mixed' if mx[k] else 'fp64'}")
         log(f"bench: {prec} davidson {it} it ({st['mixed_iters']} mixed), {t_dav:.2f} s, "
             f"time-to-1e-6 {t_1e6}")
         return {"converged": bool(conv), "iterations": it, "mixed_iterations": st["mixed_iters"],

@@ -90,8 +90,16 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
  *   "max_space"   Davidson subspace limit (default 8 * block)
  *   "max_iter"    Davidson iteration limit (default 300)
  *   "tol_e"       eigenvalue change tolerance in Eh (default 1e-8)
- *   "tol_r"       residual norm tolerance (default sqrt(tol_e))
+ *   "tol_r"       residual norm tolerance, in units of max(1, |theta|) for
+ *                 each root (default sqrt(tol_e))
  *   "verbose"     0/1: per-iteration line on stderr
+ *   "pp_slab_mb"  size bound in MiB of the rebuilt four-virtual slab of the
+ *                 particle-particle term (default 4096); a smaller slab means
+ *                 more, smaller rebuild blocks
+ *   "workspace_limit"  bytes the context may allocate in total
+ *   "autotune"    GEMM tile choice: 0 = fixed heuristic, 1 = time the tile
+ *                 configurations on the first call of each shape and keep
+ *                 the fastest (default), 2 = as 1 and log the choices
  * Errors: ADC_E_ARG for an unknown key or out-of-range value. */
 int adc_set_option(adc_ctx* ctx, const char* key, double value);
 
@@ -114,7 +122,8 @@ int adc_sigma(adc_ctx* ctx, const double* X, double* Y, int nvec);
  * (steps 4-5): initial guesses are unit vectors at the smallest diagonal
  * entries unless adc_set_guess provided vectors; the diagonal
  * preconditioner (theta - D)^-1 corrects the residuals.  Converged when
- * every root changes by <= tol_e and has residual norm <= tol_r.
+ * every root changes by <= tol_e and has residual norm
+ * <= tol_r max(1, |theta|).
  * energies, spec_factors: host [nroots] (written; spec_factors may be NULL);
  * P = 2 sum_p |X_p|^2 (Eq. 50, the sum over both spin components).
  * vecs: device [nroots][dim] (written) or NULL.  n_iter: host, may be NULL.

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
+#include <array>
 #include <cstdint>
 #include <cstdio>
 #include <map>
@@ -139,6 +140,11 @@ struct Engine {
     Ext ext;
     long long gemm_flops = 0;
     bool bf16 = false;       // FP32 contractions multiply in BF16 (mixed-precision sigma)
+    // GEMM tile autotuner: shape key -> fastest tile configuration
+    bool autotune = true;
+    bool tune_log = false;
+    std::map<std::array<long long, 12>, int> tuned;
+    hipEvent_t tev[2] = {nullptr, nullptr};
     bool timing = false;     // record events around the particle-particle kernels
     double pp_ms = 0.0;      // accumulated milliseconds of those kernels
 };

@@ -106,6 +106,16 @@ int adc_set_option(adc_ctx* c, const char* key, double value) {
         c->tol_r = value;
     } else if (k == "verbose") {
         c->verbose = value != 0;
+    } else if (k == "autotune") {
+        // 0: heuristic tile choice, 1: time candidates per shape (default),
+        // 2: as 1 and log each choice on stderr
+        if (value != 0 && value != 1 && value != 2) return fail(c, ADC_E_ARG, "autotune: 0, 1 or 2");
+        c->E.autotune = value != 0;
+        c->E.tune_log = value == 2;
+    } else if (k == "pp_slab_mb") {
+        if (value < 1 || value > 1048576) return fail(c, ADC_E_ARG, "pp_slab_mb out of range");
+        c->pp_slab_bytes = (long long)(value * 1048576.0);
+        c->E.scratch.slots.erase(30);
     } else if (k == "workspace_limit") {
         if (value <= 0) return fail(c, ADC_E_ARG, "workspace_limit must be > 0");
         c->arena.limit = (size_t)value;
@@ -269,6 +279,8 @@ void adc_destroy(adc_ctx* c) {
     if (c->E.stream) (void)hipStreamSynchronize(c->E.stream);
     else (void)hipDeviceSynchronize();
     c->E.scratch.clear();
+    for (hipEvent_t& e : c->E.tev)
+        if (e) (void)hipEventDestroy(e);
     if (c->own_blas && c->E.blas) rocblas_destroy_handle(c->E.blas);
     delete c;
 }

@@ -8,13 +8,14 @@
 //   guesses: unit vectors at the `block` smallest diagonal entries (ties to the
 //            lower index) or the vectors given by adc_set_guess;
 //   converged when every root k < nroots has |theta_k - theta_k(prev)| <= tol_e
-//            and ||r_k|| <= tol_r;
+//            and ||r_k|| <= tol_r max(1, |theta_k|) (the residual bound is
+//            relative for roots beyond 1 Eh, absolute otherwise);
 //   correction d = r / (theta - D) with |theta - D| floored at 1e-8;
 //   each new direction is orthogonalised twice against V and the directions
 //   already accepted, and dropped if its norm falls below 1e-10;
 //   restart to the current `block` Ritz vectors when V would exceed max_space.
 // Mixed precision ("precision" = 1): sigma runs in reduced precision until the
-// residuals fall below max(sqrt(tol_r), 1e-3), or below 3e-3 |theta|, or stop
+// (scaled) residuals fall below max(sqrt(tol_r), 1e-3) or 3e-3, or stop
 // decreasing; the space is then rebuilt from the Ritz vectors with FP64 sigma
 // and the iteration continues in FP64 to the requested tolerance (iterative
 // refinement of the reduced-precision subspace).
@@ -342,10 +343,11 @@ int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, 
             c->hist_r.push_back(k < nbk ? rnorm[k] : NAN);
         }
         c->hist_mixed.push_back(mixed ? 1 : 0);
+        // residuals in units of max(1, |theta|): relative for large roots
         double maxde = 0.0, maxr = 0.0;
         for (int k = 0; k < nroots; ++k) {
             maxde = std::max(maxde, std::fabs(theta[k] - theta_old[k]));
-            maxr = std::max(maxr, rnorm[k]);
+            maxr = std::max(maxr, rnorm[k] / std::max(1.0, std::fabs(theta[k])));
         }
         if (c->verbose) {
             fprintf(stderr, "adc_davidson it %d m %d nbk %d %s max|dE| %.3e max|r| %.3e theta:", it, m,
@@ -353,14 +355,11 @@ int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, 
             for (int k = 0; k < nbk; ++k) fprintf(stderr, " %.10f(%.1e)", theta[k], rnorm[k]);
             fprintf(stderr, "\n");
         }
-        double rel_r = 0.0;
-        for (int k = 0; k < nroots; ++k)
-            rel_r = std::max(rel_r, rnorm[k] / std::max(1.0, std::fabs(theta[k])));
         if (mixed) {
             stall = (maxr > 0.5 * best_mixed_r) ? stall + 1 : 0;
             best_mixed_r = std::min(best_mixed_r, maxr);
         }
-        if (mixed && (maxr <= tol_switch || rel_r <= rel_switch || stall >= 3)) {
+        if (mixed && (maxr <= tol_switch || maxr <= rel_switch || stall >= 3)) {
             // FP64 refinement: rebuild the space from the Ritz vectors with FP64 sigma
             mixed = false;
             ADC_HIP(hipMemcpyAsync(d.V.p, d.X.p, (size_t)nbk * dim * sizeof(double),
@@ -383,7 +382,7 @@ int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, 
         std::vector<int> sel;
         double thr = mixed ? tol_switch : tol_r;
         for (int k = 0; k < nbk; ++k)
-            if (rnorm[k] > thr) sel.push_back(k);
+            if (rnorm[k] > thr * std::max(1.0, std::fabs(theta[k]))) sel.push_back(k);
         if (sel.empty())
             for (int k = 0; k < nroots; ++k) sel.push_back(k);
         int nsel = (int)sel.size();

@@ -277,6 +277,7 @@ ADC_PAIR_INST(float, float)
 ADC_PAIR_INST(double, float)
 ADC_PAIR_INST(float, double)
 ADC_PAIR_INST(double, bf16_t)
+ADC_PAIR_INST(bf16_t, bf16_t)
 #undef ADC_PAIR_INST
 template void zeroth_order<double>(Engine&, const double*, double*, int, long long, int,
                                    const double*, const double*, double, double);

@@ -44,8 +44,27 @@ template <typename TI, typename T, typename TO>
 void mfma_gemm(hipStream_t st, bool ta, bool tb, long long M, long long N, long long K,
                typename AccOf<T>::type alpha, const TI* A, long long lda, long long sA, const TI* B,
                long long ldb, long long sB, typename AccOf<T>::type beta, TO* C, GemmOut out,
-               long long batch, int kind = 0);
+               long long batch, int kind = 0, int cfg = -1);
+
+// Tile configurations compiled for compute type T (ids as in gemm_tile_dims);
+// returns the count written to ids[] (at most 8).
+template <typename T> int gemm_candidates(int* ids);
+
+// mfma_gemm with the tile configuration chosen by the autotuner (tensor.hip):
+// the first call of each shape times every candidate configuration on the
+// stream (in place when beta = 0, else on a scratch output) and caches the
+// fastest; later calls of the shape use it.
+template <typename TI, typename T, typename TO>
+void gemm_run(Engine& E, bool ta, bool tb, long long M, long long N, long long K,
+              typename AccOf<T>::type alpha, const TI* A, long long lda, long long sA,
+              const TI* B, long long ldb, long long sB, typename AccOf<T>::type beta, TO* C,
+              GemmOut out, long long batch, int kind = 0);
 // kind only names the kernel in profiles: 0 plain, 1 four-index rebuild,
 // 2 particle-particle contraction (1 and 2 are NT only)
+
+// Tile configuration override for tuning (-1: automatic choice per shape) and
+// the tile of a configuration id; returns -1 for an unknown id.
+void gemm_force_config(int cfg);
+int gemm_tile_dims(int cfg, int* bm, int* bn);
 
 }  // namespace adc

@@ -1,0 +1,500 @@
+// Hand-written CDNA4 (gfx950) matrix-core GEMM used by the particle-particle
+// term and the large contractions of sigma.
+//
+//   C[perm(m, n)] = alpha * sum_k opA(A)[m][k] * opB(B)[k][n] + beta * C[...]
+//
+// A is addressed as [m][k] (row-major, k fastest) unless transposed ([k][m]);
+// B is addressed as [n][k] ("NT", k fastest) unless given as [k][n].  Both
+// operands are staged through LDS as [row][k] tiles; the k-fastest forms load
+// 16-byte vectors straight into that layout, the other forms transpose while
+// writing LDS.  Accumulation is in the MFMA accumulator type (FP64 for FP64,
+// FP32 for FP32 and BF16 inputs).
+//
+// Instruction shapes (one 64-lane wave, a 16x16 output block per instruction):
+//   FP64  v_mfma_f64_16x16x4f64       k = 4 per instruction
+//   FP32  v_mfma_f32_16x16x4f32       k = 4
+//   BF16  v_mfma_f32_16x16x32_bf16    k = 32 (8 per lane)
+// Lane l holds operand rows (l mod 16) and a k-slice chosen by l / 16; result
+// register r holds column (l mod 16) and row 4*(l/16)+r (FP32 accumulators)
+// or row (l/16)+4r (FP64 accumulators), r = 0..3.  Since only
+// the sum over k matters, each lane's k-slice within a BK tile is a contiguous
+// run of BK/4 elements (32 bytes), read from LDS with two 16-byte loads.
+//
+// The output index map supports the permuted store of the rebuilt
+// four-index block: row m = (m1, m2) with m2 = m mod rsplit, column
+// n = (n1, n2) with n2 = n mod csplit, and
+//   C offset = m1*rs1 + m2*rs2 + n1*cs1 + n2*cs2 + batch*sC.
+#pragma once
+
+#include "mfma_gemm.hpp"
+
+#include <algorithm>
+#include <type_traits>
+
+namespace adc {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<double> {
+    using acc_t = double;
+    using accv = d4v;
+    static constexpr int BK = 16;       // k per LDS tile (4 per lane: 32 bytes)
+    static constexpr int KSTEP = 4;     // k per instruction
+    // result register r of lane l holds row (l/16) + 4r (rows interleaved)
+    static __device__ __forceinline__ int row(int lg, int r) { return lg + 4 * r; }
+    static __device__ __forceinline__ accv step(const uint4* la, const uint4* lb, int s, accv c) {
+        double a = reinterpret_cast<const double*>(la)[s];
+        double b = reinterpret_cast<const double*>(lb)[s];
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+template <>
+struct Mfma<float> {
+    using acc_t = float;
+    using accv = f4v;
+    static constexpr int BK = 32;       // 8 per lane
+    static constexpr int KSTEP = 4;
+    // result register r of lane l holds row 4(l/16) + r
+    static __device__ __forceinline__ int row(int lg, int r) { return 4 * lg + r; }
+    static __device__ __forceinline__ accv step(const uint4* la, const uint4* lb, int s, accv c) {
+        float a = reinterpret_cast<const float*>(la)[s];
+        float b = reinterpret_cast<const float*>(lb)[s];
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+template <>
+struct Mfma<bf16_t> {
+    using acc_t = float;
+    using accv = f4v;
+    static constexpr int BK = 64;       // 16 per lane
+    static constexpr int KSTEP = 32;
+    static __device__ __forceinline__ int row(int lg, int r) { return 4 * lg + r; }
+    static __device__ __forceinline__ accv step(const uint4* la, const uint4* lb, int s, accv c) {
+        bf8v a = __builtin_bit_cast(bf8v, la[s]);
+        bf8v b = __builtin_bit_cast(bf8v, lb[s]);
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <typename TO, typename TA>
+__device__ __forceinline__ TO to_out(TA v) {
+    return (TO)v;
+}
+
+// A 16-byte chunk of VW compute-type elements read from storage type TI
+// (the same type, or FP32 rounded to BF16 on the way into LDS).
+template <typename TI, typename TC>
+struct Chunk {
+    static constexpr int VW = 16 / sizeof(TC);
+    static __device__ __forceinline__ uint4 vec(const TI* p) {
+        if constexpr (sizeof(TI) == sizeof(TC)) {
+            return *reinterpret_cast<const uint4*>(p);
+        } else {
+            static_assert(sizeof(TI) == 4 && sizeof(TC) == 2, "FP32 -> BF16 only");
+            TC v[VW];
+#pragma unroll
+            for (int h = 0; h < VW / 4; ++h) {
+                float4 f = reinterpret_cast<const float4*>(p)[h];
+                v[4 * h + 0] = (TC)f.x;
+                v[4 * h + 1] = (TC)f.y;
+                v[4 * h + 2] = (TC)f.z;
+                v[4 * h + 3] = (TC)f.w;
+            }
+            return __builtin_bit_cast(uint4, v);
+        }
+    }
+};
+
+// One workgroup of 256 threads (4 waves) computes a BM x BN tile; each wave a
+// WM x WN sub-tile of 16x16 instruction blocks.
+// A workgroup of WGM x WGN waves computes a BM x BN tile, each wave a
+// (BM/WGM) x (BN/WGN) block of 16x16 instruction tiles.  KIND only names the
+// kernel for profiles (0 plain, 1 four-index rebuild, 2 particle-particle
+// contraction); the code is the same.
+template <typename TI, typename T, typename TO, int BM, int BN, int WGM, int WGN, bool TA, bool TB,
+          int KIND>
+__global__ void __launch_bounds__(64 * WGM * WGN)
+k_gemm(const TI* __restrict__ A, const TI* __restrict__ B, TO* __restrict__ C, GemmShape g,
+       typename Mfma<T>::acc_t alpha, typename Mfma<T>::acc_t beta) {
+    using MT = Mfma<T>;
+    using acc_t = typename MT::acc_t;
+    using accv = typename MT::accv;
+    constexpr int NT = 64 * WGM * WGN;               // threads
+    constexpr int BK = MT::BK;
+    constexpr int VW = 16 / sizeof(T);               // elements per 16-byte vector
+    constexpr int LDK = BK + VW;                     // padded LDS row (elements)
+    constexpr int WAVES_N = WGN;
+    constexpr int WM = BM / WGM, WN = BN / WGN;
+    constexpr int TM = WM / 16, TN = WN / 16;
+    constexpr int NSTEP = BK / MT::KSTEP;
+    static_assert(TM >= 1 && TN >= 1, "tile too small");
+
+    __shared__ __attribute__((aligned(16))) T sA[2][BM * LDK];
+    __shared__ __attribute__((aligned(16))) T sB[2][BN * LDK];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+    const int li = lane & 15, lg = lane >> 4;
+
+    // tile coordinates: workgroups are dealt round-robin to the 8 XCDs, so
+    // regroup the linear id so that each XCD gets a contiguous run of tiles,
+    // then walk that run in column groups of 8 row tiles (operand reuse in L2)
+    const long long ntm = (g.M + BM - 1) / BM, ntn = (g.N + BN - 1) / BN;
+    long long pid = blockIdx.x;
+    const long long nwg = (long long)gridDim.x;
+    if ((nwg & 7) == 0) pid = (pid & 7) * (nwg >> 3) + (pid >> 3);
+    const long long GROUP = 8;
+    const long long per_group = GROUP * ntn;
+    const long long grp = pid / per_group;
+    const long long first_m = grp * GROUP;
+    const long long gsz = std::min(ntm - first_m, GROUP);
+    const long long tmi = first_m + (pid % per_group) % gsz;
+    const long long tni = (pid % per_group) / gsz;
+    const long long m0 = tmi * BM, n0 = tni * BN;
+
+    const long long bz = blockIdx.z;
+    A += bz * g.sA;
+    B += bz * g.sB;
+    C += bz * g.sC;
+
+    // ---- global -> register staging ------------------------------------
+    // A chunk is 16 bytes of compute-type elements: VW consecutive k of one
+    // row ([row][k] source) or VW consecutive rows of one k ([k][row] source).
+    constexpr int CA = BM * BK / VW / NT;   // chunks per thread (A)
+    constexpr int CB = BN * BK / VW / NT;
+    static_assert(CA >= 1 && CB >= 1 && CA * NT * VW == BM * BK && CB * NT * VW == BN * BK,
+                  "tile does not split into 16-byte chunks per thread");
+    uint4 ra[CA], rb[CB];
+
+    // unguarded 16-byte loads (interior tiles, aligned rows, full k-tile)
+    auto load_fast = [&](const TI* P, long long ld, auto trans_tag, long long R0, int R, uint4* r,
+                         int nchunk, long long k0) {
+        constexpr bool TR = decltype(trans_tag)::value;
+#pragma unroll
+        for (int c = 0; c < nchunk; ++c) {
+            const int id = tid + c * NT;
+            if constexpr (!TR) {
+                const int row = id / (BK / VW), kc = (id % (BK / VW)) * VW;
+                r[c] = Chunk<TI, T>::vec(P + (R0 + row) * ld + k0 + kc);
+            } else {
+                const int kk = id / (R / VW), rc = (id % (R / VW)) * VW;
+                r[c] = Chunk<TI, T>::vec(P + (k0 + kk) * ld + R0 + rc);
+            }
+        }
+    };
+    // element loads with bounds checks, branch-free: an out-of-range element
+    // reads P[0] and is replaced by zero
+    auto load_safe = [&](const TI* P, long long ld, auto trans_tag, long long R0, long long Rmax,
+                         int R, uint4* r, int nchunk, long long k0) {
+        constexpr bool TR = decltype(trans_tag)::value;
+#pragma unroll
+        for (int c = 0; c < nchunk; ++c) {
+            const int id = tid + c * NT;
+            T v[VW];
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+                long long gr, gk;
+                if constexpr (!TR) {
+                    gr = R0 + id / (BK / VW);
+                    gk = k0 + (id % (BK / VW)) * VW + e;
+                } else {
+                    gk = k0 + id / (R / VW);
+                    gr = R0 + (id % (R / VW)) * VW + e;
+                }
+                const bool ok = gr < Rmax && gk < g.K;
+                const long long off = TR ? gk * ld + gr : gr * ld + gk;
+                const TI x = P[ok ? off : 0];
+                v[e] = ok ? (T)x : T(0);
+            }
+            r[c] = __builtin_bit_cast(uint4, v);
+        }
+    };
+    auto store = [&](T* S, auto trans_tag, int R, const uint4* r, int nchunk) {
+        constexpr bool TR = decltype(trans_tag)::value;
+#pragma unroll
+        for (int c = 0; c < nchunk; ++c) {
+            const int id = tid + c * NT;
+            if constexpr (!TR) {
+                const int row = id / (BK / VW), kc = (id % (BK / VW)) * VW;
+                *reinterpret_cast<uint4*>(S + row * LDK + kc) = r[c];
+            } else {
+                const int kk = id / (R / VW), rc = (id % (R / VW)) * VW;
+                T v[VW];
+                *reinterpret_cast<uint4*>(v) = r[c];
+#pragma unroll
+                for (int e = 0; e < VW; ++e) S[(rc + e) * LDK + kk] = v[e];
+            }
+        }
+    };
+    using TrA = std::integral_constant<bool, TA>;
+    using TrB = std::integral_constant<bool, !TB>;
+
+    accv acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = accv{};
+
+    auto compute = [&](int cur) {
+        // fragments: each lane's contiguous k-run of BK/4 elements (32 bytes)
+        if constexpr (sizeof(T) == 8) {
+#pragma unroll
+            for (int s = 0; s < NSTEP; ++s) {
+                double fa[TM], fb[TN];
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+                    fa[i] = *reinterpret_cast<const double*>(
+                        sA[cur] + (wm * WM + i * 16 + li) * LDK + lg * (BK / 4) + s);
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    fb[j] = *reinterpret_cast<const double*>(
+                        sB[cur] + (wn * WN + j * 16 + li) * LDK + lg * (BK / 4) + s);
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j],
+                                                                         0, 0, 0);
+                // keep the next step's fragment reads from being hoisted (their
+                // registers would push the accumulators out of place)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else if constexpr (sizeof(T) == 2) {
+            // BF16: one 16-byte fragment per tile and step
+#pragma unroll
+            for (int s = 0; s < NSTEP; ++s) {
+                uint4 fa[TM], fb[TN];
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+                    fa[i] = *reinterpret_cast<const uint4*>(
+                        sA[cur] + (wm * WM + i * 16 + li) * LDK + lg * (BK / 4) + s * 8);
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    fb[j] = *reinterpret_cast<const uint4*>(
+                        sB[cur] + (wn * WN + j * 16 + li) * LDK + lg * (BK / 4) + s * 8);
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            __builtin_bit_cast(bf8v, fa[i]), __builtin_bit_cast(bf8v, fb[j]),
+                            acc[i][j], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+            uint4 fa[TM][2], fb[TN][2];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const T* p = sA[cur] + (wm * WM + i * 16 + li) * LDK + lg * (BK / 4);
+                fa[i][0] = reinterpret_cast<const uint4*>(p)[0];
+                fa[i][1] = reinterpret_cast<const uint4*>(p)[1];
+            }
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const T* p = sB[cur] + (wn * WN + j * 16 + li) * LDK + lg * (BK / 4);
+                fb[j][0] = reinterpret_cast<const uint4*>(p)[0];
+                fb[j][1] = reinterpret_cast<const uint4*>(p)[1];
+            }
+#pragma unroll
+            for (int s = 0; s < NSTEP; ++s)
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) acc[i][j] = MT::step(fa[i], fb[j], s, acc[i][j]);
+        }
+    };
+
+    // k-tiles that need no bounds checks: all full tiles of an interior,
+    // vector-aligned block; the rest (ragged k tail, edge blocks) are guarded
+    const long long nk = (g.K + BK - 1) / BK;
+    const bool interior = g.vecA && g.vecB && m0 + BM <= g.M && n0 + BN <= g.N;
+    const long long nfast = interior ? g.K / BK : 0;
+    if (nk > 0) {
+        if (nfast > 0) {
+            load_fast(A, g.lda, TrA{}, m0, BM, ra, CA, 0);
+            load_fast(B, g.ldb, TrB{}, n0, BN, rb, CB, 0);
+        } else {
+            load_safe(A, g.lda, TrA{}, m0, g.M, BM, ra, CA, 0);
+            load_safe(B, g.ldb, TrB{}, n0, g.N, BN, rb, CB, 0);
+        }
+        store(sA[0], TrA{}, BM, ra, CA);
+        store(sB[0], TrB{}, BN, rb, CB);
+        __syncthreads();
+        long long kt = 0;
+        // the next tile is a fast one
+        for (; kt + 1 < nfast; ++kt) {
+            const int cur = kt & 1;
+            load_fast(A, g.lda, TrA{}, m0, BM, ra, CA, (kt + 1) * BK);
+            load_fast(B, g.ldb, TrB{}, n0, BN, rb, CB, (kt + 1) * BK);
+            compute(cur);
+            store(sA[cur ^ 1], TrA{}, BM, ra, CA);
+            store(sB[cur ^ 1], TrB{}, BN, rb, CB);
+            __syncthreads();
+        }
+        // the next tile needs bounds checks
+        for (; kt + 1 < nk; ++kt) {
+            const int cur = kt & 1;
+            load_safe(A, g.lda, TrA{}, m0, g.M, BM, ra, CA, (kt + 1) * BK);
+            load_safe(B, g.ldb, TrB{}, n0, g.N, BN, rb, CB, (kt + 1) * BK);
+            compute(cur);
+            store(sA[cur ^ 1], TrA{}, BM, ra, CA);
+            store(sB[cur ^ 1], TrB{}, BN, rb, CB);
+            __syncthreads();
+        }
+        compute(kt & 1);
+    }
+
+    // ---- epilogue -------------------------------------------------------
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const long long m = m0 + wm * WM + i * 16 + MT::row(lg, r);
+            if (m >= g.M) continue;
+            const long long m1 = m / g.rsplit, m2 = m - m1 * g.rsplit;
+            const long long rowoff = m1 * g.rs1 + m2 * g.rs2;
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const long long n = n0 + wn * WN + j * 16 + li;
+                if (n >= g.N) continue;
+                const long long n1 = n / g.csplit, n2 = n - n1 * g.csplit;
+                TO* dst = C + rowoff + n1 * g.cs1 + n2 * g.cs2;
+                acc_t v = alpha * acc[i][j][r];
+                if (beta != acc_t(0)) v += beta * (acc_t)(*dst);
+                *dst = to_out<TO, acc_t>(v);
+            }
+        }
+    }
+}
+
+static bool aligned16(const void* p) {
+    return (reinterpret_cast<uintptr_t>(p) & 15) == 0;
+}
+
+template <typename TI, typename T, typename TO, int BM, int BN, int WGM, int WGN, int KIND>
+static void launch_tiles(hipStream_t st, bool ta, bool tb, const TI* A, const TI* B, TO* C,
+                         const GemmShape& g, long long batch, typename Mfma<T>::acc_t alpha,
+                         typename Mfma<T>::acc_t beta) {
+    const long long ntm = (g.M + BM - 1) / BM, ntn = (g.N + BN - 1) / BN;
+    ADC_REQUIRE(ntm * ntn < (1LL << 31), "gemm: grid too large");
+    constexpr int NT = 64 * WGM * WGN;
+    // the batch index runs over grid z (at most 65535 per launch)
+    for (long long z0 = 0; z0 < batch; z0 += 65535) {
+        const long long nz = std::min<long long>(65535, batch - z0);
+        const TI* Az = A + z0 * g.sA;
+        const TI* Bz = B + z0 * g.sB;
+        TO* Cz = C + z0 * g.sC;
+        dim3 grid((unsigned)(ntm * ntn), 1, (unsigned)nz);
+        if (KIND != 0 || (!ta && tb))
+            hipLaunchKernelGGL((k_gemm<TI, T, TO, BM, BN, WGM, WGN, false, true, KIND>), grid,
+                               dim3(NT), 0, st, Az, Bz, Cz, g, alpha, beta);
+        else if (!ta && !tb)
+            hipLaunchKernelGGL((k_gemm<TI, T, TO, BM, BN, WGM, WGN, false, false, 0>), grid,
+                               dim3(NT), 0, st, Az, Bz, Cz, g, alpha, beta);
+        else if (ta && !tb)
+            hipLaunchKernelGGL((k_gemm<TI, T, TO, BM, BN, WGM, WGN, true, false, 0>), grid,
+                               dim3(NT), 0, st, Az, Bz, Cz, g, alpha, beta);
+        else
+            hipLaunchKernelGGL((k_gemm<TI, T, TO, BM, BN, WGM, WGN, true, true, 0>), grid,
+                               dim3(NT), 0, st, Az, Bz, Cz, g, alpha, beta);
+        ADC_HIP(hipGetLastError());
+    }
+}
+
+// Tile configurations: (BM, BN, waves in M, waves in N).
+//   0: 64x64 (4x1)    1: 128x128 (2x2)   2: 128x128 (4x2)   3: 128x64 (2x2)
+//   4: 256x128 (2x2)  5: 256x256 (2x2)   6: 256x128 (4x2)
+
+// configurations compiled for each compute type (the rest fall back to 0)
+template <typename T> static bool cfg_available(int cfg);
+template <> inline bool cfg_available<double>(int cfg) { return cfg == 0 || cfg == 2 || cfg == 3; }
+template <> inline bool cfg_available<float>(int cfg) { return cfg == 0 || cfg == 1 || cfg == 2; }
+template <> inline bool cfg_available<bf16_t>(int cfg) { return cfg == 0 || cfg == 1 || cfg == 6; }
+
+// untuned choice: the large tile when both sides fill it and the grid gives
+// the chip at least two rounds of workgroups, else 64x64
+template <typename T>
+static int choose_cfg(long long M, long long N, long long batch) {
+    auto wgs = [&](int bm, int bn) { return ((M + bm - 1) / bm) * ((N + bn - 1) / bn) * batch; };
+    const bool big = M >= 256 && N >= 256 && wgs(128, 128) >= 512;
+    if (sizeof(T) == 8) return big ? 2 : 0;
+    return big ? 1 : 0;
+}
+
+extern int g_force_cfg;   // tuning override (all types), -1: automatic
+
+template <typename TI, typename T, typename TO>
+void mfma_gemm(hipStream_t st, bool ta, bool tb, long long M, long long N, long long K,
+               typename AccOf<T>::type alpha, const TI* A, long long lda, long long sA, const TI* B,
+               long long ldb, long long sB, typename AccOf<T>::type beta, TO* C, GemmOut out,
+               long long batch, int kind, int cfg_req) {
+    if (M <= 0 || N <= 0 || batch <= 0) return;
+    ADC_REQUIRE(kind == 0 || (!ta && tb), "gemm: tagged kernels are NT only");
+    ADC_REQUIRE(K >= 0 && lda >= (ta ? M : K) && ldb >= (tb ? K : N), "gemm: leading dimension");
+    ADC_REQUIRE(A && B && C, "gemm: null operand");
+    GemmShape g;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.lda = lda;
+    g.ldb = ldb;
+    g.sA = sA;
+    g.sB = sB;
+    g.sC = out.sC;
+    g.rsplit = out.rsplit > 0 ? out.rsplit : M;
+    g.rs1 = out.rs1;
+    g.rs2 = out.rs2;
+    g.csplit = out.csplit > 0 ? out.csplit : N;
+    g.cs1 = out.cs1;
+    g.cs2 = out.cs2;
+    constexpr int VW = 16 / sizeof(T);
+    g.vecA = aligned16(A) && (lda % VW == 0) && (batch == 1 || sA % VW == 0);
+    g.vecB = aligned16(B) && (ldb % VW == 0) && (batch == 1 || sB % VW == 0);
+    if (K <= 0) {
+        // nothing to accumulate: C = beta C through the same epilogue
+        g.K = 0;
+    }
+    // tile choice: 128x128 for large problems, 64x64 when the grid would be small
+    int cfg = g_force_cfg >= 0 ? g_force_cfg : cfg_req >= 0 ? cfg_req : choose_cfg<T>(M, N, batch);
+    if (!cfg_available<T>(cfg)) cfg = 0;
+#define ADC_CFG(ID, BM, BN, WM, WN)                                                             \
+    case ID:                                                                                    \
+        if (kind == 1)                                                                          \
+            launch_tiles<TI, T, TO, BM, BN, WM, WN, 1>(st, ta, tb, A, B, C, g, batch, alpha, beta); \
+        else if (kind == 2)                                                                     \
+            launch_tiles<TI, T, TO, BM, BN, WM, WN, 2>(st, ta, tb, A, B, C, g, batch, alpha, beta); \
+        else                                                                                    \
+            launch_tiles<TI, T, TO, BM, BN, WM, WN, 0>(st, ta, tb, A, B, C, g, batch, alpha, beta); \
+        break;
+    if constexpr (sizeof(T) == 8) {
+        switch (cfg) {
+            ADC_CFG(2, 128, 128, 4, 2)
+            ADC_CFG(3, 128, 64, 2, 2)
+            default: ADC_CFG(0, 64, 64, 4, 1)
+        }
+    } else if constexpr (sizeof(T) == 4) {
+        switch (cfg) {
+            ADC_CFG(1, 128, 128, 2, 2)
+            ADC_CFG(2, 128, 128, 4, 2)
+            default: ADC_CFG(0, 64, 64, 4, 1)
+        }
+    } else {
+        switch (cfg) {
+            ADC_CFG(1, 128, 128, 2, 2)
+            ADC_CFG(6, 256, 128, 4, 2)
+            default: ADC_CFG(0, 64, 64, 4, 1)
+        }
+    }
+#undef ADC_CFG
+}
+
+}  // namespace adc

@@ -80,6 +80,85 @@ void permute(Engine& E, T alpha, const char* si, const T* in, T beta, const char
 // ---------------------------------------------------------------------------
 // GEMM (row-major view over column-major rocBLAS)
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// GEMM autotuner
+// ---------------------------------------------------------------------------
+template <typename TI, typename T, typename TO>
+void gemm_run(Engine& E, bool ta, bool tb, long long M, long long N, long long K,
+              typename AccOf<T>::type alpha, const TI* A, long long lda, long long sA,
+              const TI* B, long long ldb, long long sB, typename AccOf<T>::type beta, TO* C,
+              GemmOut out, long long batch, int kind) {
+    using Acc = typename AccOf<T>::type;
+    if (M <= 0 || N <= 0 || batch <= 0) return;
+    const std::array<long long, 12> key{(long long)sizeof(TI), (long long)sizeof(T),
+                                        (long long)sizeof(TO), ta, tb, M, N, K, batch, kind,
+                                        out.rsplit > 0, out.csplit > 0};
+    auto it = E.tuned.find(key);
+    if (it != E.tuned.end()) {
+        mfma_gemm<TI, T, TO>(E.stream, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,
+                             out, batch, kind, it->second);
+        return;
+    }
+    const double flops = 2.0 * M * N * K * batch;
+    const size_t cbytes = sizeof(TO) * (size_t)M * N * batch;
+    if (!E.autotune || flops < 2e8 || (beta != Acc(0) && cbytes > (size_t(512) << 20))) {
+        mfma_gemm<TI, T, TO>(E.stream, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,
+                             out, batch, kind, -1);
+        return;
+    }
+    // trials: in place when the product overwrites C, else on a scratch output
+    TO* Ct = C;
+    GemmOut ot = out;
+    Acc bt = beta;
+    if (beta != Acc(0)) {
+        Ct = (TO*)E.scratch.get(28, cbytes);
+        ot = GemmOut::rowmajor(N, M * N);
+        bt = Acc(0);
+    }
+    if (!E.tev[0]) {
+        ADC_HIP(hipEventCreate(&E.tev[0]));
+        ADC_HIP(hipEventCreate(&E.tev[1]));
+    }
+    int ids[8];
+    const int n = gemm_candidates<T>(ids);
+    float best = 3.0e38f;
+    int bc = ids[0];
+    for (int k = 0; k < n; ++k) {
+        ADC_HIP(hipEventRecord(E.tev[0], E.stream));
+        mfma_gemm<TI, T, TO>(E.stream, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, bt, Ct, ot,
+                             batch, kind, ids[k]);
+        ADC_HIP(hipEventRecord(E.tev[1], E.stream));
+        ADC_HIP(hipEventSynchronize(E.tev[1]));
+        float ms = 0.f;
+        ADC_HIP(hipEventElapsedTime(&ms, E.tev[0], E.tev[1]));
+        if (ms < best) {
+            best = ms;
+            bc = ids[k];
+        }
+    }
+    E.tuned[key] = bc;
+    if (E.tune_log)
+        fprintf(stderr, "gemm tune: in %d B cmp %d B out %d B %c%c M %lld N %lld K %lld batch %lld "
+                "kind %d -> config %d (%.3f ms, %.1f TFLOP/s)\n",
+                (int)sizeof(TI), (int)sizeof(T), (int)sizeof(TO), ta ? 'T' : 'N', tb ? 'T' : 'N',
+                M, N, K, batch, kind, bc, best, flops / (best * 1e-3) / 1e12);
+    if (Ct != C)
+        mfma_gemm<TI, T, TO>(E.stream, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,
+                             out, batch, kind, bc);
+}
+
+#define ADC_RUN_INST(TI, T, TO)                                                                  \
+    template void gemm_run<TI, T, TO>(Engine&, bool, bool, long long, long long, long long,      \
+                                      AccOf<T>::type, const TI*, long long, long long, const TI*, \
+                                      long long, long long, AccOf<T>::type, TO*, GemmOut,         \
+                                      long long, int);
+ADC_RUN_INST(double, double, double)
+ADC_RUN_INST(float, float, float)
+ADC_RUN_INST(float, bf16_t, float)
+ADC_RUN_INST(bf16_t, bf16_t, float)
+ADC_RUN_INST(bf16_t, bf16_t, bf16_t)
+#undef ADC_RUN_INST
+
 // Skinny products with a long summed index (Davidson overlaps, gemv-like
 // contractions) would leave most of the chip idle: split K into chunks run as
 // one batched GEMM into partial results, then reduce them in a fixed order.
@@ -114,11 +193,11 @@ static void gemm_any(Engine& E, bool ta, bool tb, long long M, long long N, long
             Acc* part = (Acc*)E.scratch.get(31, sizeof(Acc) * S * M * N);
             const long long offA = ta ? Kc * lda : Kc, offB = tb ? Kc : Kc * ldb;
             if (S > 1)
-                mfma_gemm<TI, T, Acc>(E.stream, ta, tb, M, N, Kc, (Acc)alpha, A, lda, offA, B,
-                                      ldb, offB, Acc(0), part, GemmOut::rowmajor(N, M * N), S - 1);
-            mfma_gemm<TI, T, Acc>(E.stream, ta, tb, M, N, Klast, (Acc)alpha, A + (S - 1) * offA,
-                                  lda, 0, B + (S - 1) * offB, ldb, 0, Acc(0),
-                                  part + (S - 1) * M * N, GemmOut::rowmajor(N), 1);
+                gemm_run<TI, T, Acc>(E, ta, tb, M, N, Kc, (Acc)alpha, A, lda, offA, B, ldb, offB,
+                                     Acc(0), part, GemmOut::rowmajor(N, M * N), S - 1);
+            gemm_run<TI, T, Acc>(E, ta, tb, M, N, Klast, (Acc)alpha, A + (S - 1) * offA, lda, 0,
+                                 B + (S - 1) * offB, ldb, 0, Acc(0), part + (S - 1) * M * N,
+                                 GemmOut::rowmajor(N), 1);
             long long g = (M * N + 255) / 256;
             if (g > 4096) g = 4096;
             hipLaunchKernelGGL(k_splitk_reduce<Acc>, dim3((unsigned)g), dim3(256), 0, E.stream,
@@ -127,8 +206,8 @@ static void gemm_any(Engine& E, bool ta, bool tb, long long M, long long N, long
             return;
         }
     }
-    mfma_gemm<TI, T, TI>(E.stream, ta, tb, M, N, K, (Acc)alpha, A, lda, sA, B, ldb, sB, (Acc)beta, C,
-                         GemmOut::rowmajor(ldc, sC), batch);
+    gemm_run<TI, T, TI>(E, ta, tb, M, N, K, (Acc)alpha, A, lda, sA, B, ldb, sB, (Acc)beta, C,
+                        GemmOut::rowmajor(ldc, sC), batch);
 }
 
 template <>
