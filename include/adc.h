@@ -97,6 +97,8 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
  *                 particle-particle term (default 4096); a smaller slab means
  *                 more, smaller rebuild blocks
  *   "workspace_limit"  bytes the context may allocate in total
+ *   "record"      keep up to this many Davidson iterates for training pairs
+ *   "precond"     0 = diagonal preconditioner, 1 = the installed network
  *   "autotune"    GEMM tile choice: 0 = fixed heuristic, 1 = time the tile
  *                 configurations on the first call of each shape and keep
  *                 the fastest (default), 2 = as 1 and log the choices
@@ -175,6 +177,63 @@ void adc_destroy(adc_ctx* ctx);
  * (vectors), mixed-precision iterations, wall seconds.  host arrays. */
 int adc_last_stats(const adc_ctx* ctx, int* iters, long long* sigma_vectors,
                    int* mixed_iters, double* seconds);
+
+/* ---- learned preconditioner --------------------------------------------
+ * Not in the paper: an extension of its Davidson correction (Sec. III.A,
+ * step 4).  The diagonal correction r / (theta - D) is multiplied element
+ * by element by (1 + y), y the output of a 3-layer perceptron (width 256,
+ * tanh) fed with 7 local features of the element (theta - D, the
+ * normalised residual, the element's orbital energies, theta, the block);
+ * the exact definitions, the FP32 parameter layout and the training target
+ * are in csrc/mlp.hip.  The diagonal preconditioner stays the fallback. */
+
+/* Number of FP32 parameters of the network (68097). */
+long long adc_mlp_nparams(void);
+
+/* Install a network for later adc_davidson calls of ctx (params: device
+ * [adc_mlp_nparams()] FP32, copied) and select it; NULL restores the
+ * diagonal preconditioner.  A solve whose learned corrections turn
+ * non-finite, or whose residuals stop falling (four iterations without a
+ * 10% decrease), goes
+ * on with the diagonal one (counted by adc_mlp_status).  Option "precond"
+ * (0/1) switches between an installed network and the diagonal. */
+int adc_precond_mlp(adc_ctx* ctx, const float* params, long long nparams);
+int adc_mlp_status(const adc_ctx* ctx, int* installed, int* fallbacks);
+
+/* Training pairs for nidx sampled elements (idx: device [nidx], each in
+ * [0, dim)) of one Davidson iterate: x its Ritz vector and r its residual
+ * (device [dim]), theta its Ritz value, xstar the converged eigenvector of
+ * the same root (device [dim]).  Writes F: device [nidx][7] features,
+ * a: device [nidx] rhat*q (the diagonal correction of the normalised
+ * residual), t: device [nidx] target.  ADC_E_ARG for a zero vector. */
+int adc_mlp_pairs(adc_ctx* ctx, const double* x, const double* r, double theta,
+                  const double* xstar, const long long* idx, long long nidx, float* F,
+                  float* a, float* t);
+
+/* y[n] = network output for features F[n][7] (device).  bf16 != 0: the
+ * hidden 256x256 layer multiplies in BF16 with FP32 sums (inference);
+ * else FP32 throughout. */
+int adc_mlp_forward(adc_ctx* ctx, const float* params, const float* F, long long n, int bf16,
+                    float* y);
+
+/* loss = 0.5 mean_e (a_e (1 + y_e) - t_e)^2 over n pairs (host output) and
+ * its gradient grad[adc_mlp_nparams()] (device) with respect to params,
+ * FP32 forward and backward. */
+int adc_mlp_loss_grad(adc_ctx* ctx, const float* params, const float* F, const float* a,
+                      const float* t, long long n, float* grad, double* loss);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; step >= 1)
+ * on params with first/second moments m, v (all device FP32 vectors of
+ * adc_mlp_nparams() entries, updated in place). */
+int adc_mlp_adam(adc_ctx* ctx, float* params, const float* grad, float* m, float* v, int step,
+                 double lr);
+
+/* Iterates recorded by the last adc_davidson call (option "record" = how
+ * many, 0 by default): count, and entry i: Ritz vector x and residual r
+ * (device [dim] outputs, either may be NULL), Ritz value and root index
+ * (host outputs, may be NULL). */
+int adc_record_count(const adc_ctx* ctx);
+int adc_record_get(adc_ctx* ctx, int i, double* x, double* r, double* theta, int* root);
 
 #ifdef __cplusplus
 }

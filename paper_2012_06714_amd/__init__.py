@@ -21,7 +21,9 @@ ADC_OK, ADC_E_ARG, ADC_E_OOM, ADC_E_HIP, ADC_E_STATE, ADC_E_NUMERIC, ADC_E_NOCON
 ABI_SYMBOLS = ("adc_setup", "adc_set_option", "adc_set_stream", "adc_dim", "adc_diag",
                "adc_sigma", "adc_davidson", "adc_spec_factors", "adc_set_guess",
                "adc_last_error", "adc_destroy", "adc_last_stats", "adc_sigma_flops",
-               "adc_sigma_timed", "adc_history")
+               "adc_sigma_timed", "adc_history", "adc_mlp_nparams", "adc_precond_mlp",
+               "adc_mlp_status", "adc_mlp_pairs", "adc_mlp_forward", "adc_mlp_loss_grad",
+               "adc_mlp_adam", "adc_record_count", "adc_record_get")
 
 
 class ADCError(RuntimeError):
@@ -51,6 +53,15 @@ def _load():
         "adc_sigma_flops": (i, [vp, i, vp, vp]),
         "adc_sigma_timed": (i, [vp, vp, vp, i, vp, vp]),
         "adc_history": (i, [vp, i, vp, vp, vp, vp]),
+        "adc_mlp_nparams": (ll, []),
+        "adc_precond_mlp": (i, [vp, vp, ll]),
+        "adc_mlp_status": (i, [vp, vp, vp]),
+        "adc_mlp_pairs": (i, [vp, vp, vp, d, vp, vp, ll, vp, vp, vp]),
+        "adc_mlp_forward": (i, [vp, vp, vp, ll, i, vp]),
+        "adc_mlp_loss_grad": (i, [vp, vp, vp, vp, vp, ll, vp, vp]),
+        "adc_mlp_adam": (i, [vp, vp, vp, vp, vp, i, d]),
+        "adc_record_count": (i, [vp]),
+        "adc_record_get": (i, [vp, i, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -191,6 +202,74 @@ class Context:
                                   ctypes.byref(sec)), self._h)
         return {"iters": it.value, "sigma_vectors": sv.value, "mixed_iters": mi.value,
                 "seconds": sec.value}
+
+    # ---- learned preconditioner ------------------------------------------
+    def precond_mlp(self, params):
+        """Install FP32 device parameters (or None for the diagonal one)."""
+        torch = self._torch
+        if params is None:
+            _check(lib.adc_precond_mlp(self._h, None, 0), self._h)
+        else:
+            _check(lib.adc_precond_mlp(self._h, _dev(params, torch, torch.float32),
+                                       params.numel()), self._h)
+
+    def mlp_status(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(lib.adc_mlp_status(self._h, ctypes.byref(a), ctypes.byref(b)), self._h)
+        return bool(a.value), b.value
+
+    def mlp_pairs(self, x, r, theta, xstar, idx):
+        """Features F [n, 7], a [n], t [n] (float32 device) for sampled elements."""
+        torch = self._torch
+        n = idx.numel()
+        F = torch.empty((n, 7), dtype=torch.float32, device="cuda")
+        a = torch.empty(n, dtype=torch.float32, device="cuda")
+        t = torch.empty(n, dtype=torch.float32, device="cuda")
+        _check(lib.adc_mlp_pairs(self._h, _dev(x, torch), _dev(r, torch), float(theta),
+                                 _dev(xstar, torch), _dev(idx, torch, torch.int64), n,
+                                 _dev(F, torch, torch.float32), _dev(a, torch, torch.float32),
+                                 _dev(t, torch, torch.float32)), self._h)
+        return F, a, t
+
+    def mlp_forward(self, params, F, bf16=False):
+        torch = self._torch
+        y = torch.empty(F.shape[0], dtype=torch.float32, device="cuda")
+        _check(lib.adc_mlp_forward(self._h, _dev(params, torch, torch.float32),
+                                   _dev(F, torch, torch.float32), F.shape[0], int(bf16),
+                                   _dev(y, torch, torch.float32)), self._h)
+        return y
+
+    def mlp_loss_grad(self, params, F, a, t, grad=None):
+        torch = self._torch
+        if grad is None:
+            grad = torch.empty_like(params)
+        loss = ctypes.c_double()
+        f32 = torch.float32
+        _check(lib.adc_mlp_loss_grad(self._h, _dev(params, torch, f32), _dev(F, torch, f32),
+                                     _dev(a, torch, f32), _dev(t, torch, f32), F.shape[0],
+                                     _dev(grad, torch, f32), ctypes.byref(loss)), self._h)
+        return loss.value, grad
+
+    def mlp_adam(self, params, grad, m, v, step, lr):
+        torch = self._torch
+        f32 = torch.float32
+        _check(lib.adc_mlp_adam(self._h, _dev(params, torch, f32), _dev(grad, torch, f32),
+                                _dev(m, torch, f32), _dev(v, torch, f32), int(step), float(lr)),
+               self._h)
+
+    def records(self):
+        """Recorded iterates of the last solve: list of (x, r, theta, root)."""
+        torch = self._torch
+        n = lib.adc_record_count(self._h)
+        out = []
+        for i in range(n):
+            x = torch.empty(self.dim, dtype=torch.float64, device="cuda")
+            r = torch.empty_like(x)
+            th, rt = ctypes.c_double(), ctypes.c_int()
+            _check(lib.adc_record_get(self._h, i, _dev(x, torch), _dev(r, torch),
+                                      ctypes.byref(th), ctypes.byref(rt)), self._h)
+            out.append((x, r, th.value, rt.value))
+        return out
 
     def close(self):
         if getattr(self, "_h", None):

@@ -106,6 +106,16 @@ int adc_set_option(adc_ctx* c, const char* key, double value) {
         c->tol_r = value;
     } else if (k == "verbose") {
         c->verbose = value != 0;
+    } else if (k == "record") {
+        // Davidson iterates (Ritz vector, residual, value) kept for training pairs
+        if (value < 0 || value > 100000) return fail(c, ADC_E_ARG, "record out of range");
+        c->record_max = (int)value;
+    } else if (k == "precond") {
+        // 0: diagonal; 1: the installed learned correction (adc_precond_mlp)
+        if (value != 0 && value != 1) return fail(c, ADC_E_ARG, "precond: 0 or 1");
+        if (value == 1 && !c->mlp_params.p)
+            return fail(c, ADC_E_STATE, "precond: no network installed (adc_precond_mlp)");
+        c->use_mlp = value == 1;
     } else if (k == "autotune") {
         // 0: heuristic tile choice, 1: time candidates per shape (default),
         // 2: as 1 and log each choice on stderr
@@ -258,6 +268,104 @@ int adc_sigma_timed(adc_ctx* c, const double* X, double* Y, int nvec, double* ms
         if (ms_pp) *ms_pp = c->E.pp_ms;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        return ADC_OK;
+    });
+}
+
+// ---- learned preconditioner -----------------------------------------------
+long long adc_mlp_nparams(void) { return adc::MLP_NPARAM; }
+
+int adc_precond_mlp(adc_ctx* c, const float* params, long long nparams) {
+    if (!c) return fail(nullptr, ADC_E_ARG, "adc_precond_mlp: NULL context");
+    if (!params) {
+        c->use_mlp = false;
+        c->mlp_params.release();
+        return ADC_OK;
+    }
+    if (nparams != adc::MLP_NPARAM)
+        return fail(c, ADC_E_ARG, "adc_precond_mlp: nparams must equal adc_mlp_nparams()");
+    return guarded(c, [&]() {
+        c->mlp_params.alloc((size_t)nparams, &c->arena);
+        ADC_HIP(hipMemcpyAsync(c->mlp_params.p, params, nparams * sizeof(float),
+                               hipMemcpyDeviceToDevice, c->E.stream));
+        ADC_HIP(hipStreamSynchronize(c->E.stream));
+        c->use_mlp = true;
+        return ADC_OK;
+    });
+}
+
+int adc_mlp_status(const adc_ctx* c, int* installed, int* fallbacks) {
+    if (!c) return fail(nullptr, ADC_E_ARG, "adc_mlp_status: NULL context");
+    if (installed) *installed = c->use_mlp ? 1 : 0;
+    if (fallbacks) *fallbacks = c->mlp_fallbacks;
+    return ADC_OK;
+}
+
+int adc_mlp_pairs(adc_ctx* c, const double* x, const double* r, double theta, const double* xstar,
+                  const long long* idx, long long nidx, float* F, float* a, float* t) {
+    if (!c) return fail(nullptr, ADC_E_ARG, "adc_mlp_pairs: NULL context");
+    if (!x || !r || !xstar || !idx || !F || !a || !t || nidx < 1 || !std::isfinite(theta))
+        return fail(c, ADC_E_ARG, "adc_mlp_pairs: bad arguments");
+    return guarded(c, [&]() {
+        adc::mlp_pairs(c, x, r, theta, xstar, idx, nidx, F, a, t);
+        ADC_HIP(hipStreamSynchronize(c->E.stream));
+        return ADC_OK;
+    });
+}
+
+int adc_mlp_forward(adc_ctx* c, const float* params, const float* F, long long n, int bf16,
+                    float* y) {
+    if (!c) return fail(nullptr, ADC_E_ARG, "adc_mlp_forward: NULL context");
+    if (!params || !F || !y || n < 1) return fail(c, ADC_E_ARG, "adc_mlp_forward: bad arguments");
+    return guarded(c, [&]() {
+        adc::mlp_forward(c, params, F, n, bf16 != 0, y);
+        ADC_HIP(hipStreamSynchronize(c->E.stream));
+        return ADC_OK;
+    });
+}
+
+int adc_mlp_loss_grad(adc_ctx* c, const float* params, const float* F, const float* a,
+                      const float* t, long long n, float* grad, double* loss) {
+    if (!c) return fail(nullptr, ADC_E_ARG, "adc_mlp_loss_grad: NULL context");
+    if (!params || !F || !a || !t || !grad || n < 1)
+        return fail(c, ADC_E_ARG, "adc_mlp_loss_grad: bad arguments");
+    return guarded(c, [&]() {
+        double l = adc::mlp_loss_grad(c, params, F, a, t, n, grad);
+        if (loss) *loss = l;
+        return ADC_OK;
+    });
+}
+
+int adc_mlp_adam(adc_ctx* c, float* params, const float* grad, float* m, float* v, int step,
+                 double lr) {
+    if (!c) return fail(nullptr, ADC_E_ARG, "adc_mlp_adam: NULL context");
+    if (!params || !grad || !m || !v || step < 1 || !(lr > 0))
+        return fail(c, ADC_E_ARG, "adc_mlp_adam: bad arguments");
+    return guarded(c, [&]() {
+        adc::mlp_adam(c, params, grad, m, v, adc::MLP_NPARAM, step, lr);
+        ADC_HIP(hipStreamSynchronize(c->E.stream));
+        return ADC_OK;
+    });
+}
+
+int adc_record_count(const adc_ctx* c) {
+    if (!c) return fail(nullptr, ADC_E_ARG, "adc_record_count: NULL context");
+    return c->nrec;
+}
+
+int adc_record_get(adc_ctx* c, int i, double* x, double* r, double* theta, int* root) {
+    if (!c) return fail(nullptr, ADC_E_ARG, "adc_record_get: NULL context");
+    if (i < 0 || i >= c->nrec) return fail(c, ADC_E_ARG, "adc_record_get: index out of range");
+    return guarded(c, [&]() {
+        if (x)
+            ADC_HIP(hipMemcpyAsync(x, c->rec_x.p + (size_t)i * c->dim, c->dim * sizeof(double),
+                                   hipMemcpyDeviceToDevice, c->E.stream));
+        if (r)
+            ADC_HIP(hipMemcpyAsync(r, c->rec_r.p + (size_t)i * c->dim, c->dim * sizeof(double),
+                                   hipMemcpyDeviceToDevice, c->E.stream));
+        ADC_HIP(hipStreamSynchronize(c->E.stream));
+        if (theta) *theta = c->rec_theta[i];
+        if (root) *root = c->rec_root[i];
         return ADC_OK;
     });
 }

@@ -50,6 +50,19 @@ struct adc_ctx {
     bool mixed_ready = false;
     long long pp_slab_bytes = 4LL << 30;   // rebuilt four-index slab (particle-particle term)
 
+    // learned preconditioner (mlp.hip): installed parameters, or diagonal
+    double escale = 1.0;                  // max |eps|, the feature energy scale
+    adc::DBuf<float> mlp_params;
+    bool use_mlp = false;
+    int mlp_fallbacks = 0;                // solves that fell back to the diagonal
+
+    // Davidson iterates recorded for training pairs (Ritz vector, residual, value)
+    int record_max = 0;
+    int nrec = 0;
+    adc::DBuf<double> rec_x, rec_r;
+    std::vector<double> rec_theta;
+    std::vector<int> rec_root;
+
     // statistics and convergence history of the last solve
     int hist_nroots = 0;
     std::vector<double> hist_t, hist_theta, hist_r;
@@ -80,6 +93,20 @@ void sigma_cost(const adc_ctx* c, int nvec, double* total, double* pp);
 
 // spec.hip
 void spec_amplitudes(adc_ctx* c, const double* vecs, int nvec, double* Xout /*device [nvec][N]*/);
+
+// mlp.hip: learned preconditioner (layout and features documented there)
+constexpr int MLP_NF = 7, MLP_WIDTH = 256;
+constexpr long long MLP_NPARAM = MLP_WIDTH * MLP_NF + MLP_WIDTH + MLP_WIDTH * MLP_WIDTH +
+                                 MLP_WIDTH + MLP_WIDTH + 1;
+void mlp_pairs(adc_ctx* c, const double* x, const double* r, double theta, const double* xstar,
+               const long long* idx, long long nidx, float* F, float* a, float* t);
+void mlp_forward(adc_ctx* c, const float* P, const float* F, long long n, bool bf16, float* y);
+double mlp_loss_grad(adc_ctx* c, const float* P, const float* F, const float* a, const float* t,
+                     long long n, float* G);
+void mlp_adam(adc_ctx* c, float* P, const float* G, float* m, float* v, long long np, int step,
+              double lr);
+bool mlp_precondition(adc_ctx* c, const double* R, const std::vector<double>& theta,
+                      const std::vector<int>& sel, double* Dout);
 
 // davidson.hip
 int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, int* n_iter);

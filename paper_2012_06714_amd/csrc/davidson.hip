@@ -10,7 +10,8 @@
 //   converged when every root k < nroots has |theta_k - theta_k(prev)| <= tol_e
 //            and ||r_k|| <= tol_r max(1, |theta_k|) (the residual bound is
 //            relative for roots beyond 1 Eh, absolute otherwise);
-//   correction d = r / (theta - D) with |theta - D| floored at 1e-8;
+//   correction d = r / (theta - D) with |theta - D| floored at 1e-8, or the
+//            learned correction of it (mlp.hip) when a network is installed;
 //   each new direction is orthogonalised twice against V and the directions
 //   already accepted, and dropped if its norm falls below 1e-10;
 //   restart to the current `block` Ritz vectors when V would exceed max_space.
@@ -281,6 +282,17 @@ int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, 
     c->hist_mixed.clear();
     std::vector<double> blk;
     bool converged = false;
+    bool use_mlp = c->use_mlp && c->mlp_params.p;
+    double best_mlp_r = INFINITY;
+    int mlp_stall = 0;
+    // iterates recorded for training pairs
+    c->nrec = 0;
+    c->rec_theta.clear();
+    c->rec_root.clear();
+    if (c->record_max > 0) {
+        c->rec_x.alloc((size_t)c->record_max * dim, &c->arena);
+        c->rec_r.alloc((size_t)c->record_max * dim, &c->arena);
+    }
     while (true) {
         ++it;
         // sigma for the new directions
@@ -343,6 +355,15 @@ int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, 
             c->hist_r.push_back(k < nbk ? rnorm[k] : NAN);
         }
         c->hist_mixed.push_back(mixed ? 1 : 0);
+        for (int k = 0; k < nroots && k < nbk && c->nrec < c->record_max; ++k) {
+            ADC_HIP(hipMemcpyAsync(c->rec_x.p + (size_t)c->nrec * dim, d.X.p + (size_t)k * dim,
+                                   dim * sizeof(double), hipMemcpyDeviceToDevice, E.stream));
+            ADC_HIP(hipMemcpyAsync(c->rec_r.p + (size_t)c->nrec * dim, d.R.p + (size_t)k * dim,
+                                   dim * sizeof(double), hipMemcpyDeviceToDevice, E.stream));
+            c->rec_theta.push_back(theta[k]);
+            c->rec_root.push_back(k);
+            ++c->nrec;
+        }
         // residuals in units of max(1, |theta|): relative for large roots
         double maxde = 0.0, maxr = 0.0;
         for (int k = 0; k < nroots; ++k) {
@@ -386,11 +407,26 @@ int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, 
         if (sel.empty())
             for (int k = 0; k < nroots; ++k) sel.push_back(k);
         int nsel = (int)sel.size();
-        ADC_HIP(hipMemcpyAsync(d.sel_d.p, sel.data(), nsel * sizeof(int), hipMemcpyHostToDevice,
-                               E.stream));
-        hipLaunchKernelGGL(k_precond, dim3(nb_((long long)nsel * dim)), dim3(256), 0, E.stream,
-                           d.R.p, c->diag.p, d.th.p, d.sel_d.p, d.D.p, dim, nsel);
-        ADC_HIP(hipGetLastError());
+        // learned correction of the diagonal preconditioner while it behaves:
+        // a non-finite output, or residuals that stop falling (four
+        // iterations without a 10% decrease), switch to the diagonal one
+        if (use_mlp) {
+            mlp_stall = (maxr > 0.9 * best_mlp_r) ? mlp_stall + 1 : 0;
+            best_mlp_r = std::min(best_mlp_r, maxr);
+            if (mlp_stall >= 4) use_mlp = false;
+        }
+        bool done = false;
+        if (use_mlp) {
+            done = mlp_precondition(c, d.R.p, theta, sel, d.D.p);
+            if (!done) use_mlp = false;
+        }
+        if (!done) {
+            ADC_HIP(hipMemcpyAsync(d.sel_d.p, sel.data(), nsel * sizeof(int),
+                                   hipMemcpyHostToDevice, E.stream));
+            hipLaunchKernelGGL(k_precond, dim3(nb_((long long)nsel * dim)), dim3(256), 0,
+                               E.stream, d.R.p, c->diag.p, d.th.p, d.sel_d.p, d.D.p, dim, nsel);
+            ADC_HIP(hipGetLastError());
+        }
         if (m + nsel > max_space) {
             // restart from the current Ritz vectors
             ADC_HIP(hipMemcpyAsync(d.V.p, d.X.p, (size_t)nbk * dim * sizeof(double),
@@ -416,6 +452,7 @@ int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, 
         m += kept;
     }
     (void)converged;
+    if (c->use_mlp && !use_mlp) c->mlp_fallbacks++;
     for (int k = 0; k < nroots; ++k) energies[k] = theta[k];
     if (vecs)
         ADC_HIP(hipMemcpyAsync(vecs, d.X.p, (size_t)nroots * dim * sizeof(double),

@@ -14,6 +14,10 @@
 //   M11            EA: [a][b]  IP: [i][j]
 #include "context.hpp"
 
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
 namespace adc {
 
 namespace {
@@ -47,6 +51,15 @@ void setup_all(adc_ctx* c, const double* eps, const double* B) {
     c->ev.alloc(V, &c->arena);
     ADC_HIP(hipMemcpyAsync(c->eo.p, eps, O * sizeof(double), hipMemcpyDeviceToDevice, E.stream));
     ADC_HIP(hipMemcpyAsync(c->ev.p, eps + O, V * sizeof(double), hipMemcpyDeviceToDevice, E.stream));
+    {
+        // energy scale of the learned preconditioner's features: max |eps|
+        std::vector<double> h(N);
+        ADC_HIP(hipMemcpyAsync(h.data(), eps, N * sizeof(double), hipMemcpyDeviceToHost, E.stream));
+        ADC_HIP(hipStreamSynchronize(E.stream));
+        double s = 0.0;
+        for (double v : h) s = std::max(s, std::fabs(v));
+        c->escale = s > 0.0 ? s : 1.0;
+    }
 
     // ---- step 1: B blocks (Q fastest) -------------------------------------
     c->Boo.alloc(OO * Q, &c->arena);

@@ -415,6 +415,7 @@ template void permute<double>(Engine&, double, const char*, const double*, doubl
 template void permute<float>(Engine&, float, const char*, const float*, float, const char*, float*);
 template void fill<double>(Engine&, double*, double, size_t);
 template void fill<float>(Engine&, float*, float, size_t);
+template void fill<int>(Engine&, int*, int, size_t);
 template void axpy<double>(Engine&, double, const double*, double*, size_t);
 template void axpy<float>(Engine&, float, const float*, float*, size_t);
 

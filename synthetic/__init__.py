@@ -84,6 +84,23 @@ def draw_batch_sizes(rng: np.random.Generator):
     return nocc, nvir, 3 * nvir
 
 
+def make_batch_system(system: int, max_nocc: int | None = None):
+    """System `system` of the batched EA-ADC(2) workload (index 5): sizes drawn
+    by draw_batch_sizes, then eps and B, all from seed_for(5, system).  Systems
+    0..63 are the evaluation batch, 100..299 the training set.  max_nocc caps
+    nocc (smaller stand-ins for quick checks; the cap is applied to the drawn
+    value, the rest of the recipe is unchanged)."""
+    seed = seed_for(5, system)
+    rng = np.random.default_rng(seed)
+    nocc, nvir, naux = draw_batch_sizes(rng)
+    if max_nocc is not None and nocc > max_nocc:
+        nvir = int(round(nvir * max_nocc / nocc))
+        nocc = max_nocc
+        naux = 3 * nvir
+    eps, B = draw_system(nocc, nvir, naux, seed, rng)
+    return eps, B, (nocc, nvir, naux)
+
+
 def make_system(key: str, system: int = 0):
     """Inputs of a named workload: returns (eps, B, workload)."""
     w = WORKLOADS[key]
