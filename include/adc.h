@@ -97,6 +97,8 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
  *                 particle-particle term (default 4096); a smaller slab means
  *                 more, smaller rebuild blocks
  *   "workspace_limit"  bytes the context may allocate in total
+ *   "graph"       1 = replay sigma from HIP graphs captured per (vector
+ *                 count, precision) after an eager warm-up call (default 0)
  *   "record"      keep up to this many Davidson iterates for training pairs
  *   "precond"     0 = diagonal preconditioner, 1 = the installed network
  *   "autotune"    GEMM tile choice: 0 = fixed heuristic, 1 = time the tile
@@ -177,6 +179,9 @@ void adc_destroy(adc_ctx* ctx);
  * (vectors), mixed-precision iterations, wall seconds.  host arrays. */
 int adc_last_stats(const adc_ctx* ctx, int* iters, long long* sigma_vectors,
                    int* mixed_iters, double* seconds);
+
+/* Number of sigma graph replays so far (option "graph"); -1 for NULL. */
+long long adc_graph_launches(const adc_ctx* ctx);
 
 /* ---- learned preconditioner --------------------------------------------
  * Not in the paper: an extension of its Davidson correction (Sec. III.A,

@@ -23,7 +23,7 @@ ABI_SYMBOLS = ("adc_setup", "adc_set_option", "adc_set_stream", "adc_dim", "adc_
                "adc_last_error", "adc_destroy", "adc_last_stats", "adc_sigma_flops",
                "adc_sigma_timed", "adc_history", "adc_mlp_nparams", "adc_precond_mlp",
                "adc_mlp_status", "adc_mlp_pairs", "adc_mlp_forward", "adc_mlp_loss_grad",
-               "adc_mlp_adam", "adc_record_count", "adc_record_get")
+               "adc_mlp_adam", "adc_record_count", "adc_record_get", "adc_graph_launches")
 
 
 class ADCError(RuntimeError):
@@ -62,6 +62,7 @@ def _load():
         "adc_mlp_adam": (i, [vp, vp, vp, vp, vp, i, d]),
         "adc_record_count": (i, [vp]),
         "adc_record_get": (i, [vp, i, vp, vp, vp, vp]),
+        "adc_graph_launches": (ll, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -202,6 +203,9 @@ class Context:
                                   ctypes.byref(sec)), self._h)
         return {"iters": it.value, "sigma_vectors": sv.value, "mixed_iters": mi.value,
                 "seconds": sec.value}
+
+    def graph_launches(self):
+        return int(lib.adc_graph_launches(self._h))
 
     # ---- learned preconditioner ------------------------------------------
     def precond_mlp(self, params):

@@ -108,17 +108,32 @@ void DBuf<T>::release() {
 }
 
 // Scratch slots reused by the contraction helper (grown on demand).
+// While `touched` is set, get() records each slot used with its address and
+// size: work recorded with those addresses (a captured graph) stays valid as
+// long as every recorded slot still has that address and at least that size.
 struct Scratch {
     std::map<int, DBuf<char>> slots;
     Arena* arena = nullptr;
+    std::map<int, std::pair<void*, size_t>>* touched = nullptr;
     void* get(int slot, size_t bytes) {
         auto& b = slots[slot];
         if (b.n < bytes) {
             b.release();
             b.alloc(bytes + bytes / 8, arena);
         }
+        if (touched) (*touched)[slot] = {b.p, b.n};
         return b.p;
     }
+    bool still_valid(const std::map<int, std::pair<void*, size_t>>& rec) const {
+        for (const auto& kv : rec) {
+            auto it = slots.find(kv.first);
+            if (it == slots.end() || it->second.p != kv.second.first ||
+                it->second.n < kv.second.second)
+                return false;
+        }
+        return true;
+    }
+    void erase(int slot) { slots.erase(slot); }
     void clear() { slots.clear(); }
 };
 

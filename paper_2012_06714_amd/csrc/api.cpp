@@ -106,6 +106,11 @@ int adc_set_option(adc_ctx* c, const char* key, double value) {
         c->tol_r = value;
     } else if (k == "verbose") {
         c->verbose = value != 0;
+    } else if (k == "graph") {
+        // 1: replay sigma from a captured HIP graph per (vector count, precision)
+        if (value != 0 && value != 1) return fail(c, ADC_E_ARG, "graph: 0 or 1");
+        c->use_graph = value == 1;
+        if (!c->use_graph) adc::drop_graphs(c);
     } else if (k == "record") {
         // Davidson iterates (Ritz vector, residual, value) kept for training pairs
         if (value < 0 || value > 100000) return fail(c, ADC_E_ARG, "record out of range");
@@ -125,7 +130,7 @@ int adc_set_option(adc_ctx* c, const char* key, double value) {
     } else if (k == "pp_slab_mb") {
         if (value < 1 || value > 1048576) return fail(c, ADC_E_ARG, "pp_slab_mb out of range");
         c->pp_slab_bytes = (long long)(value * 1048576.0);
-        c->E.scratch.slots.erase(30);
+        c->E.scratch.erase(30);
     } else if (k == "workspace_limit") {
         if (value <= 0) return fail(c, ADC_E_ARG, "workspace_limit must be > 0");
         c->arena.limit = (size_t)value;
@@ -348,6 +353,8 @@ int adc_mlp_adam(adc_ctx* c, float* params, const float* grad, float* m, float* 
     });
 }
 
+long long adc_graph_launches(const adc_ctx* c) { return c ? c->graph_launches : -1; }
+
 int adc_record_count(const adc_ctx* c) {
     if (!c) return fail(nullptr, ADC_E_ARG, "adc_record_count: NULL context");
     return c->nrec;
@@ -386,6 +393,12 @@ void adc_destroy(adc_ctx* c) {
     if (!c) return;
     if (c->E.stream) (void)hipStreamSynchronize(c->E.stream);
     else (void)hipDeviceSynchronize();
+    adc::drop_graphs(c);
+    if (c->gstream) {
+        (void)hipStreamSynchronize(c->gstream);
+        (void)hipStreamDestroy(c->gstream);
+    }
+    if (c->gdone) (void)hipEventDestroy(c->gdone);
     c->E.scratch.clear();
     for (hipEvent_t& e : c->E.tev)
         if (e) (void)hipEventDestroy(e);

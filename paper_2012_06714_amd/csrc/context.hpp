@@ -50,6 +50,20 @@ struct adc_ctx {
     bool mixed_ready = false;
     long long pp_slab_bytes = 4LL << 30;   // rebuilt four-index slab (particle-particle term)
 
+    // sigma replayed from captured HIP graphs (sigma.hip)
+    struct SigmaGraph {
+        int nvec = 0, precision = 0;
+        std::map<int, std::pair<void*, size_t>> slots;   // scratch used by the capture
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    bool use_graph = false;
+    hipStream_t gstream = nullptr;   // capture stream when the context runs on the null stream
+    hipEvent_t gdone = nullptr;      // marks the end of a replay on gstream
+    std::vector<SigmaGraph> graphs;
+    adc::DBuf<double> Xg, Yg;     // the captured graphs' input and output
+    long long graph_launches = 0;
+
     // learned preconditioner (mlp.hip): installed parameters, or diagonal
     double escale = 1.0;                  // max |eps|, the feature energy scale
     adc::DBuf<float> mlp_params;
@@ -89,6 +103,7 @@ void sigma_block(adc_ctx* c, const double* X, double* Y, int nvec);
 template <typename T, typename TO>
 void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx);
 void sigma(adc_ctx* c, const double* X, double* Y, int nvec, int precision);
+void drop_graphs(adc_ctx* c);
 void sigma_cost(const adc_ctx* c, int nvec, double* total, double* pp);
 
 // spec.hip

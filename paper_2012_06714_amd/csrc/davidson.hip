@@ -475,7 +475,7 @@ int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, 
     if (n_iter) *n_iter = it;
     c->st_iters = it;
     c->st_seconds = std::chrono::duration<double>(clk::now() - t0).count();
-    E.scratch.clear();
+    E.scratch.clear();    // also invalidates captured sigma graphs
     return status;
 }
 

@@ -266,6 +266,105 @@ void sigma_block(adc_ctx* c, const double* X, double* Yout, int nvec) {
     pair_transform<T, double>(E, S2, len2, 0, Yout, dim, n1, nvec, nx, np, AL, BE, beta2);
 }
 
+static void sigma_eager(adc_ctx* c, const double* X, double* Y, int nvec, int precision) {
+    if (precision == 1)
+        sigma_block<float>(c, X, Y, nvec);
+    else
+        sigma_block<double>(c, X, Y, nvec);
+}
+
+void drop_graphs(adc_ctx* c) {
+    for (auto& g : c->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    c->graphs.clear();
+}
+
+// sigma replayed from a HIP graph.  The graph is captured over the internal
+// buffers Xg -> Yg after an eager warm-up call with the same sizes (which
+// allocates every scratch buffer and settles the GEMM autotuner, so the
+// captured region holds kernel launches only); it is re-captured when one of
+// the scratch buffers it uses has been reallocated or freed since.
+static void sigma_graph(adc_ctx* c, const double* X, double* Y, int nvec, int precision) {
+    Engine& E = c->E;
+    // the null stream cannot be captured: use a blocking stream of the
+    // context's own (default priority), ordered with null-stream work
+    struct StreamScope {
+        Engine& e;
+        hipStream_t old;
+        ~StreamScope() { e.stream = old; }
+    } scope{E, E.stream};
+    const bool own = !E.stream;
+    if (own) {
+        if (!c->gstream) ADC_HIP(hipStreamCreate(&c->gstream));
+        if (!c->gdone) ADC_HIP(hipEventCreateWithFlags(&c->gdone, hipEventDisableTiming));
+        E.stream = c->gstream;
+    }
+    const size_t bytes = (size_t)nvec * c->dim * sizeof(double);
+    if (c->Xg.n < (size_t)nvec * c->dim) {
+        drop_graphs(c);
+        c->Xg.alloc((size_t)nvec * c->dim, &c->arena);
+        c->Yg.alloc((size_t)nvec * c->dim, &c->arena);
+    }
+    ADC_HIP(hipMemcpyAsync(c->Xg.p, X, bytes, hipMemcpyDeviceToDevice, E.stream));
+    adc_ctx::SigmaGraph* g = nullptr;
+    for (auto& e : c->graphs)
+        if (e.nvec == nvec && e.precision == precision) g = &e;
+    if (g && g->exec && !E.scratch.still_valid(g->slots)) {
+        (void)hipGraphExecDestroy(g->exec);
+        (void)hipGraphDestroy(g->graph);
+        g->exec = nullptr;
+        g->graph = nullptr;
+    }
+    if (!g || !g->exec) {
+        // warm-up, then capture
+        sigma_eager(c, c->Xg.p, c->Yg.p, nvec, precision);
+        ADC_HIP(hipStreamSynchronize(E.stream));
+        std::map<int, std::pair<void*, size_t>> used;
+        const bool tune = E.autotune;
+        E.autotune = false;          // shapes are tuned by now; no timing inside the capture
+        E.scratch.touched = &used;
+        hipGraph_t graph = nullptr;
+        ADC_HIP(hipStreamBeginCapture(E.stream, hipStreamCaptureModeThreadLocal));
+        try {
+            sigma_eager(c, c->Xg.p, c->Yg.p, nvec, precision);
+        } catch (...) {
+            hipGraph_t dead = nullptr;
+            (void)hipStreamEndCapture(E.stream, &dead);
+            if (dead) (void)hipGraphDestroy(dead);
+            E.autotune = tune;
+            E.scratch.touched = nullptr;
+            throw;
+        }
+        ADC_HIP(hipStreamEndCapture(E.stream, &graph));
+        E.autotune = tune;
+        E.scratch.touched = nullptr;
+        // the warm-up sized every buffer: nothing may have moved in the capture
+        std::map<int, std::pair<void*, size_t>> before = used;
+        ADC_REQUIRE(E.scratch.still_valid(before), "sigma graph: scratch moved during capture");
+        hipGraphExec_t exec = nullptr;
+        ADC_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        if (!g) {
+            c->graphs.emplace_back();
+            g = &c->graphs.back();
+        }
+        g->nvec = nvec;
+        g->precision = precision;
+        g->slots = used;
+        g->graph = graph;
+        g->exec = exec;
+    }
+    ADC_HIP(hipGraphLaunch(g->exec, E.stream));
+    ++c->graph_launches;
+    ADC_HIP(hipMemcpyAsync(Y, c->Yg.p, bytes, hipMemcpyDeviceToDevice, E.stream));
+    if (own) {
+        // later null-stream work (and its synchronisations) wait for the replay
+        ADC_HIP(hipEventRecord(c->gdone, c->gstream));
+        ADC_HIP(hipStreamWaitEvent(nullptr, c->gdone, 0));
+    }
+}
+
 void sigma(adc_ctx* c, const double* X, double* Y, int nvec, int precision) {
     // process in chunks to bound the scratch footprint
     const int chunk = 64;
@@ -273,10 +372,10 @@ void sigma(adc_ctx* c, const double* X, double* Y, int nvec, int precision) {
         int nz = nvec - z0 < chunk ? nvec - z0 : chunk;
         const double* Xz = X + (long long)z0 * c->dim;
         double* Yz = Y + (long long)z0 * c->dim;
-        if (precision == 1)
-            sigma_block<float>(c, Xz, Yz, nz);
+        if (c->use_graph && !c->E.timing)
+            sigma_graph(c, Xz, Yz, nz, precision);
         else
-            sigma_block<double>(c, Xz, Yz, nz);
+            sigma_eager(c, Xz, Yz, nz, precision);
     }
 }
 
