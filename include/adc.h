@@ -180,6 +180,24 @@ void adc_destroy(adc_ctx* ctx);
 int adc_last_stats(const adc_ctx* ctx, int* iters, long long* sigma_vectors,
                    int* mixed_iters, double* seconds);
 
+/* Several systems solved together (not in the paper: batching of its step 4
+ * over independent systems).  ctxs: nsys distinct contexts, each set up and
+ * configured as for adc_davidson; their solvers advance in lockstep and each
+ * iteration applies sigma to the new trial vectors of every active system in
+ * one HIP graph launch (use_graph != 0; the graph has one branch per system
+ * on a few default-priority streams and is re-captured when the set of
+ * active systems or their vector counts change), or system by system
+ * (use_graph = 0).  Results equal those of adc_davidson on each context.
+ * energies, spec_factors: host [nsys][nroots] (spec_factors may be NULL);
+ * n_iter, status: host [nsys] (may be NULL; status per system as
+ * adc_davidson returns it); stats: host [3] or NULL: lockstep iterations,
+ * graph launches, graph captures.  Returns ADC_OK when every system
+ * converged, else the first non-OK status; the message of a failure is
+ * adc_last_error(NULL). */
+int adc_batch_davidson(adc_ctx* const* ctxs, int nsys, int nroots, int use_graph,
+                       double* energies, double* spec_factors, int* n_iter, int* status,
+                       long long* stats);
+
 /* Number of sigma graph replays so far (option "graph"); -1 for NULL. */
 long long adc_graph_launches(const adc_ctx* ctx);
 

@@ -23,7 +23,8 @@ ABI_SYMBOLS = ("adc_setup", "adc_set_option", "adc_set_stream", "adc_dim", "adc_
                "adc_last_error", "adc_destroy", "adc_last_stats", "adc_sigma_flops",
                "adc_sigma_timed", "adc_history", "adc_mlp_nparams", "adc_precond_mlp",
                "adc_mlp_status", "adc_mlp_pairs", "adc_mlp_forward", "adc_mlp_loss_grad",
-               "adc_mlp_adam", "adc_record_count", "adc_record_get", "adc_graph_launches")
+               "adc_mlp_adam", "adc_record_count", "adc_record_get", "adc_graph_launches",
+               "adc_batch_davidson")
 
 
 class ADCError(RuntimeError):
@@ -63,6 +64,7 @@ def _load():
         "adc_record_count": (i, [vp]),
         "adc_record_get": (i, [vp, i, vp, vp, vp, vp]),
         "adc_graph_launches": (ll, [vp]),
+        "adc_batch_davidson": (i, [vp, i, i, i, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -89,6 +91,29 @@ def _dev(x, torch, dtype=None):
     if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == dtype and x.is_contiguous()):
         raise TypeError("expected a contiguous CUDA tensor of dtype %s" % dtype)
     return ctypes.c_void_p(x.data_ptr())
+
+
+def batch_davidson(contexts, nroots, use_graph=True):
+    """Solve several systems together (adc_batch_davidson).  Returns
+    (energies [nsys][nroots], P [nsys][nroots], iterations [nsys],
+    statuses [nsys], stats {iterations, graph_launches, captures})."""
+    import numpy as np
+    n = len(contexts)
+    arr = (ctypes.c_void_p * n)(*[c._h.value if isinstance(c._h, ctypes.c_void_p) else c._h
+                                  for c in contexts])
+    e = np.zeros((n, nroots))
+    P = np.zeros((n, nroots))
+    it = np.zeros(n, dtype=np.int32)
+    st = np.zeros(n, dtype=np.int32)
+    stats = np.zeros(3, dtype=np.int64)
+    rc = lib.adc_batch_davidson(arr, n, int(nroots), int(bool(use_graph)),
+                                e.ctypes.data_as(ctypes.c_void_p), P.ctypes.data_as(ctypes.c_void_p),
+                                it.ctypes.data_as(ctypes.c_void_p), st.ctypes.data_as(ctypes.c_void_p),
+                                stats.ctypes.data_as(ctypes.c_void_p))
+    if rc not in (ADC_OK, ADC_E_NOCONV):
+        raise ADCError(rc, last_error(None))
+    return e, P, it, st, {"iterations": int(stats[0]), "graph_launches": int(stats[1]),
+                          "captures": int(stats[2])}
 
 
 class Context:

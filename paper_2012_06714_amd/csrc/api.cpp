@@ -353,6 +353,32 @@ int adc_mlp_adam(adc_ctx* c, float* params, const float* grad, float* m, float* 
     });
 }
 
+int adc_batch_davidson(adc_ctx* const* ctxs, int nsys, int nroots, int use_graph,
+                       double* energies, double* spec_factors, int* n_iter, int* status,
+                       long long* stats) {
+    if (!ctxs || nsys < 1 || nroots < 1 || !energies)
+        return fail(nullptr, ADC_E_ARG, "adc_batch_davidson: bad arguments");
+    for (int k = 0; k < nsys; ++k) {
+        if (!ctxs[k]) return fail(nullptr, ADC_E_ARG, "adc_batch_davidson: NULL context");
+        if (nroots > ctxs[k]->dim)
+            return fail(nullptr, ADC_E_ARG, "adc_batch_davidson: nroots exceeds a dimension");
+        for (int j = 0; j < k; ++j)
+            if (ctxs[j] == ctxs[k])
+                return fail(nullptr, ADC_E_ARG, "adc_batch_davidson: a context appears twice");
+    }
+    return guarded(nullptr, [&]() {
+        adc::BatchStats st;
+        int rc = adc::batch_davidson(ctxs, nsys, nroots, use_graph != 0, energies, spec_factors,
+                                     n_iter, status, &st);
+        if (stats) {
+            stats[0] = st.iterations;
+            stats[1] = st.graph_launches;
+            stats[2] = st.captures;
+        }
+        return rc;
+    });
+}
+
 long long adc_graph_launches(const adc_ctx* c) { return c ? c->graph_launches : -1; }
 
 int adc_record_count(const adc_ctx* c) {

@@ -103,6 +103,7 @@ void sigma_block(adc_ctx* c, const double* X, double* Y, int nvec);
 template <typename T, typename TO>
 void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx);
 void sigma(adc_ctx* c, const double* X, double* Y, int nvec, int precision);
+void sigma_eager(adc_ctx* c, const double* X, double* Y, int nvec, int precision);  // one block
 void drop_graphs(adc_ctx* c);
 void sigma_cost(const adc_ctx* c, int nvec, double* total, double* pp);
 
@@ -125,6 +126,19 @@ bool mlp_precondition(adc_ctx* c, const double* R, const std::vector<double>& th
 
 // davidson.hip
 int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, int* n_iter);
+// batch.hip: lockstep solves of several systems, sigma of all in one graph launch
+struct BatchStats {
+    long long graph_launches = 0, captures = 0;
+    int iterations = 0;
+};
+int batch_davidson(adc_ctx* const* ctx, int nsys, int nroots, bool use_graph, double* energies,
+                   double* P, int* n_iter, int* status, BatchStats* st);
+struct Solver;   // one solve as a state machine (batched driving in batch.hip)
+Solver* solver_new(adc_ctx* c, int nroots);
+void solver_delete(Solver* s);
+bool solver_request(Solver* s, const double** X, double** W, int* nn, int* precision);
+bool solver_advance(Solver* s);
+int solver_finish(Solver* s, double* energies, double* P, double* vecs, int* n_iter);
 
 // kernels shared by setup/sigma (elementwise.hip)
 void stage_block(Engine& E, const double* B, int Q, int N, int p0, int np, int q0, int nq,

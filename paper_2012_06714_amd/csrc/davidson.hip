@@ -191,114 +191,135 @@ struct Dav {
     }
 };
 
-int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, int* n_iter) {
+// One solve as a state machine, so that several systems can advance in
+// lockstep with their sigma products batched (batch.hip):
+//   Solver s(c, nroots);  while (s.request(&X, &W, &n, &prec)) { sigma; s.advance(); }
+//   s.finish(energies, P, vecs, n_iter);
+struct Solver {
     using clk = std::chrono::steady_clock;
-    auto t0 = clk::now();
-    Engine& E = c->E;
-    const long long dim = c->dim;
-    int block = c->block > 0 ? c->block : std::max(nroots, 8);
-    block = std::max(block, nroots);
-    block = (int)std::min<long long>(block, dim);
-    int max_space = c->max_space > 0 ? c->max_space : 8 * block;
-    max_space = std::max(max_space, 2 * block);
-    max_space = (int)std::min<long long>(max_space, dim);
-    const double tol_e = c->tol_e;
-    const double tol_r = c->tol_r > 0 ? c->tol_r : std::sqrt(tol_e);
+    adc_ctx* c;
+    Engine& E;
+    int nroots;
+    long long dim;
+    int block, max_space;
+    double tol_e, tol_r, tol_switch;
+    const double rel_switch = 3e-3;
+    Dav d;
+    clk::time_point t0;
+    std::vector<double> theta_old, theta, rnorm, Gh, blk;
+    int it = 0, status = ADC_OK, m = 0, newstart = 0, nbk = 0;
+    bool mixed, use_mlp, done = false;
+    double best_mixed_r = INFINITY, best_mlp_r = INFINITY;
+    int stall = 0, mlp_stall = 0;
 
-    Dav d(c);
-    d.block = block;
-    d.max_space = max_space;
-    d.V.alloc((size_t)max_space * dim, &c->arena);
-    d.W.alloc((size_t)max_space * dim, &c->arena);
-    d.X.alloc((size_t)block * dim, &c->arena);
-    d.AX.alloc((size_t)block * dim, &c->arena);
-    d.R.alloc((size_t)block * dim, &c->arena);
-    d.D.alloc((size_t)block * dim, &c->arena);
-    d.G.alloc((size_t)max_space * max_space, &c->arena);
-    d.S.alloc((size_t)max_space * max_space, &c->arena);
-    d.th.alloc(max_space, &c->arena);
-    d.ev_e.alloc(max_space, &c->arena);
-    d.sel_d.alloc(block, &c->arena);
-    d.info.alloc(1, &c->arena);
-
-    // ---- initial space ----------------------------------------------------------
-    int m = 0, nb = 0;
-    if (c->nguess > 0) {
-        nb = std::min(c->nguess, block);
-        ADC_HIP(hipMemcpyAsync(d.V.p, c->guess.p, (size_t)nb * dim * sizeof(double),
-                               hipMemcpyDeviceToDevice, E.stream));
-        nb = d.orthonormalize(d.V.p, nb, 0);
-    }
-    if (nb < block) {
-        std::vector<double> dh(dim);
-        ADC_HIP(hipMemcpyAsync(dh.data(), c->diag.p, dim * sizeof(double), hipMemcpyDeviceToHost,
-                               E.stream));
-        ADC_HIP(hipStreamSynchronize(E.stream));
-        std::vector<long long> ord(dim);
-        std::iota(ord.begin(), ord.end(), 0LL);
-        int need = block - nb;
-        std::partial_sort(ord.begin(), ord.begin() + std::min<long long>(dim, need + nb), ord.end(),
-                          [&](long long a, long long b) {
-                              return dh[a] < dh[b] || (dh[a] == dh[b] && a < b);
-                          });
-        // unit vectors, orthogonalised against any guess vectors
-        double* Dm = d.V.p + (size_t)nb * dim;
-        fill<double>(E, Dm, 0.0, (size_t)need * dim);
-        DBuf<long long> idx;
-        idx.alloc(need, &c->arena);
-        ADC_HIP(hipMemcpyAsync(idx.p, ord.data(), need * sizeof(long long), hipMemcpyHostToDevice,
-                               E.stream));
-        hipLaunchKernelGGL(k_unit, dim3((need + 63) / 64), dim3(64), 0, E.stream, Dm, idx.p, dim,
-                           need);
-        ADC_HIP(hipGetLastError());
-        ADC_HIP(hipStreamSynchronize(E.stream));
-        if (nb > 0) {
-            int kept = d.orthonormalize(Dm, need, nb);
-            nb += kept;
-        } else {
-            nb = need;
+    Solver(adc_ctx* cc, int nr) : c(cc), E(cc->E), nroots(nr), dim(cc->dim), d(cc) {
+        t0 = clk::now();
+        block = c->block > 0 ? c->block : std::max(nroots, 8);
+        block = std::max(block, nroots);
+        block = (int)std::min<long long>(block, dim);
+        max_space = c->max_space > 0 ? c->max_space : 8 * block;
+        max_space = std::max(max_space, 2 * block);
+        max_space = (int)std::min<long long>(max_space, dim);
+        tol_e = c->tol_e;
+        tol_r = c->tol_r > 0 ? c->tol_r : std::sqrt(tol_e);
+        // leave the reduced-precision phase once the residuals reach what BF16
+        // products can resolve, or when they stop falling (three iterations
+        // without halving)
+        tol_switch = std::max(std::sqrt(tol_r), 1e-3);
+        d.block = block;
+        d.max_space = max_space;
+        d.V.alloc((size_t)max_space * dim, &c->arena);
+        d.W.alloc((size_t)max_space * dim, &c->arena);
+        d.X.alloc((size_t)block * dim, &c->arena);
+        d.AX.alloc((size_t)block * dim, &c->arena);
+        d.R.alloc((size_t)block * dim, &c->arena);
+        d.D.alloc((size_t)block * dim, &c->arena);
+        d.G.alloc((size_t)max_space * max_space, &c->arena);
+        d.S.alloc((size_t)max_space * max_space, &c->arena);
+        d.th.alloc(max_space, &c->arena);
+        d.ev_e.alloc(max_space, &c->arena);
+        d.sel_d.alloc(block, &c->arena);
+        d.info.alloc(1, &c->arena);
+        initial_space();
+        theta_old.assign(block, INFINITY);
+        theta.assign(max_space, 0.0);
+        Gh.assign((size_t)max_space * max_space, 0.0);
+        mixed = c->precision == 1;
+        use_mlp = c->use_mlp && c->mlp_params.p;
+        c->st_sigvec = 0;
+        c->st_mixed = 0;
+        c->hist_nroots = nroots;
+        c->hist_t.clear();
+        c->hist_theta.clear();
+        c->hist_r.clear();
+        c->hist_mixed.clear();
+        // iterates recorded for training pairs
+        c->nrec = 0;
+        c->rec_theta.clear();
+        c->rec_root.clear();
+        if (c->record_max > 0) {
+            c->rec_x.alloc((size_t)c->record_max * dim, &c->arena);
+            c->rec_r.alloc((size_t)c->record_max * dim, &c->arena);
         }
     }
 
-    std::vector<double> theta_old(block, INFINITY), theta(max_space), rnorm;
-    int it = 0, status = ADC_OK;
-    bool mixed = c->precision == 1;
-    // leave the reduced-precision phase once the residuals reach what BF16
-    // products can resolve: absolutely, relative to the Ritz values, or when
-    // they stop falling (three iterations without halving)
-    const double tol_switch = std::max(std::sqrt(tol_r), 1e-3);
-    const double rel_switch = 3e-3;
-    double best_mixed_r = INFINITY;
-    int stall = 0;
-    c->st_sigvec = 0;
-    c->st_mixed = 0;
-    int newstart = 0;    // first basis vector without a sigma vector
-    m = nb;
-    std::vector<double> Gh((size_t)max_space * max_space, 0.0);
-    c->hist_nroots = nroots;
-    c->hist_t.clear();
-    c->hist_theta.clear();
-    c->hist_r.clear();
-    c->hist_mixed.clear();
-    std::vector<double> blk;
-    bool converged = false;
-    bool use_mlp = c->use_mlp && c->mlp_params.p;
-    double best_mlp_r = INFINITY;
-    int mlp_stall = 0;
-    // iterates recorded for training pairs
-    c->nrec = 0;
-    c->rec_theta.clear();
-    c->rec_root.clear();
-    if (c->record_max > 0) {
-        c->rec_x.alloc((size_t)c->record_max * dim, &c->arena);
-        c->rec_r.alloc((size_t)c->record_max * dim, &c->arena);
+    void initial_space() {
+        int nb = 0;
+        if (c->nguess > 0) {
+            nb = std::min(c->nguess, block);
+            ADC_HIP(hipMemcpyAsync(d.V.p, c->guess.p, (size_t)nb * dim * sizeof(double),
+                                   hipMemcpyDeviceToDevice, E.stream));
+            nb = d.orthonormalize(d.V.p, nb, 0);
+        }
+        if (nb < block) {
+            std::vector<double> dh(dim);
+            ADC_HIP(hipMemcpyAsync(dh.data(), c->diag.p, dim * sizeof(double),
+                                   hipMemcpyDeviceToHost, E.stream));
+            ADC_HIP(hipStreamSynchronize(E.stream));
+            std::vector<long long> ord(dim);
+            std::iota(ord.begin(), ord.end(), 0LL);
+            int need = block - nb;
+            std::partial_sort(ord.begin(), ord.begin() + std::min<long long>(dim, need + nb),
+                              ord.end(), [&](long long a, long long b) {
+                                  return dh[a] < dh[b] || (dh[a] == dh[b] && a < b);
+                              });
+            // unit vectors, orthogonalised against any guess vectors
+            double* Dm = d.V.p + (size_t)nb * dim;
+            fill<double>(E, Dm, 0.0, (size_t)need * dim);
+            DBuf<long long> idx;
+            idx.alloc(need, &c->arena);
+            ADC_HIP(hipMemcpyAsync(idx.p, ord.data(), need * sizeof(long long),
+                                   hipMemcpyHostToDevice, E.stream));
+            hipLaunchKernelGGL(k_unit, dim3((need + 63) / 64), dim3(64), 0, E.stream, Dm, idx.p,
+                               dim, need);
+            ADC_HIP(hipGetLastError());
+            ADC_HIP(hipStreamSynchronize(E.stream));
+            if (nb > 0) {
+                int kept = d.orthonormalize(Dm, need, nb);
+                nb += kept;
+            } else {
+                nb = need;
+            }
+        }
+        m = nb;
+        newstart = 0;
     }
-    while (true) {
+
+    // sigma work of the coming iteration: the basis vectors without a sigma
+    // vector.  Returns false once the solve has ended.
+    bool request(const double** X, double** W, int* nn, int* precision) {
+        if (done) return false;
+        *X = d.V.p + (size_t)newstart * dim;
+        *W = d.W.p + (size_t)newstart * dim;
+        *nn = m - newstart;
+        *precision = mixed ? 1 : 0;
+        return true;
+    }
+
+    // everything after the sigma products; returns true when the solve ended
+    bool advance() {
         ++it;
-        // sigma for the new directions
-        int nn = m - newstart;
-        sigma(c, d.V.p + (size_t)newstart * dim, d.W.p + (size_t)newstart * dim, nn,
-              mixed ? 1 : 0);
+        const int nn = m - newstart;
         c->st_sigvec += nn;
         if (mixed) c->st_mixed++;
         // G rows for the new vectors: blk[nn][m] = W_new V^T
@@ -336,12 +357,12 @@ int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, 
                                   d.th.p, d.ev_e.p, d.info.p));
         ADC_HIP(hipMemcpyAsync(theta.data(), d.th.p, m * sizeof(double), hipMemcpyDeviceToHost,
                                E.stream));
-        int nbk = std::min(block, m);
+        nbk = std::min(block, m);
         // Ritz vectors: X = S^T V, AX = S^T W  (row k of S is eigenvector k)
         gemm_rm<double>(E, false, false, nbk, dim, m, 1.0, d.S.p, m, 0, d.V.p, dim, 0, 0.0, d.X.p,
                         dim, 0, 1);
-        gemm_rm<double>(E, false, false, nbk, dim, m, 1.0, d.S.p, m, 0, d.W.p, dim, 0, 0.0, d.AX.p,
-                        dim, 0, 1);
+        gemm_rm<double>(E, false, false, nbk, dim, m, 1.0, d.S.p, m, 0, d.W.p, dim, 0, 0.0,
+                        d.AX.p, dim, 0, 1);
         hipLaunchKernelGGL(k_residual, dim3(nb_((long long)nbk * dim)), dim3(256), 0, E.stream,
                            d.AX.p, d.X.p, d.th.p, d.R.p, dim, nbk);
         ADC_HIP(hipGetLastError());
@@ -371,8 +392,8 @@ int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, 
             maxr = std::max(maxr, rnorm[k] / std::max(1.0, std::fabs(theta[k])));
         }
         if (c->verbose) {
-            fprintf(stderr, "adc_davidson it %d m %d nbk %d %s max|dE| %.3e max|r| %.3e theta:", it, m,
-                    nbk, mixed ? "mixed" : "fp64", maxde, maxr);
+            fprintf(stderr, "adc_davidson it %d m %d nbk %d %s max|dE| %.3e max|r| %.3e theta:", it,
+                    m, nbk, mixed ? "mixed" : "fp64", maxde, maxr);
             for (int k = 0; k < nbk; ++k) fprintf(stderr, " %.10f(%.1e)", theta[k], rnorm[k]);
             fprintf(stderr, "\n");
         }
@@ -389,16 +410,10 @@ int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, 
             newstart = 0;
             std::fill(Gh.begin(), Gh.end(), 0.0);
             std::fill(theta_old.begin(), theta_old.end(), INFINITY);
-            continue;
+            return false;
         }
-        if (!mixed && maxde <= tol_e && maxr <= tol_r) {
-            converged = true;
-            break;
-        }
-        if (it >= c->max_iter) {
-            status = ADC_E_NOCONV;
-            break;
-        }
+        if (!mixed && maxde <= tol_e && maxr <= tol_r) return end(ADC_OK);
+        if (it >= c->max_iter) return end(ADC_E_NOCONV);
         for (int k = 0; k < nbk; ++k) theta_old[k] = theta[k];
         std::vector<int> sel;
         double thr = mixed ? tol_switch : tol_r;
@@ -415,12 +430,12 @@ int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, 
             best_mlp_r = std::min(best_mlp_r, maxr);
             if (mlp_stall >= 4) use_mlp = false;
         }
-        bool done = false;
+        bool precond_done = false;
         if (use_mlp) {
-            done = mlp_precondition(c, d.R.p, theta, sel, d.D.p);
-            if (!done) use_mlp = false;
+            precond_done = mlp_precondition(c, d.R.p, theta, sel, d.D.p);
+            if (!precond_done) use_mlp = false;
         }
-        if (!done) {
+        if (!precond_done) {
             ADC_HIP(hipMemcpyAsync(d.sel_d.p, sel.data(), nsel * sizeof(int),
                                    hipMemcpyHostToDevice, E.stream));
             hipLaunchKernelGGL(k_precond, dim3(nb_((long long)nsel * dim)), dim3(256), 0,
@@ -443,40 +458,71 @@ int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, 
             // every correction lies in the current space: the space is invariant
             // to working precision, so the Ritz pairs are converged if their
             // residuals are
-            if (!mixed && maxr <= tol_r) converged = true;
-            else status = ADC_E_NOCONV;
-            break;
+            return end((!mixed && maxr <= tol_r) ? ADC_OK : ADC_E_NOCONV);
         }
-        ADC_HIP(hipMemcpyAsync(d.V.p + (size_t)m * dim, d.D.p, (size_t)kept * dim * sizeof(double),
-                               hipMemcpyDeviceToDevice, E.stream));
-        m += kept;
-    }
-    (void)converged;
-    if (c->use_mlp && !use_mlp) c->mlp_fallbacks++;
-    for (int k = 0; k < nroots; ++k) energies[k] = theta[k];
-    if (vecs)
-        ADC_HIP(hipMemcpyAsync(vecs, d.X.p, (size_t)nroots * dim * sizeof(double),
-                               hipMemcpyDeviceToDevice, E.stream));
-    if (P) {
-        DBuf<double> Xs;
-        Xs.alloc((size_t)nroots * c->N, &c->arena);
-        spec_amplitudes(c, d.X.p, nroots, Xs.p);
-        std::vector<double> xh((size_t)nroots * c->N);
-        ADC_HIP(hipMemcpyAsync(xh.data(), Xs.p, xh.size() * sizeof(double), hipMemcpyDeviceToHost,
+        ADC_HIP(hipMemcpyAsync(d.V.p + (size_t)m * dim, d.D.p,
+                               (size_t)kept * dim * sizeof(double), hipMemcpyDeviceToDevice,
                                E.stream));
-        ADC_HIP(hipStreamSynchronize(E.stream));
-        for (int k = 0; k < nroots; ++k) {
-            double s = 0.0;
-            for (int p = 0; p < c->N; ++p) s += xh[(size_t)k * c->N + p] * xh[(size_t)k * c->N + p];
-            P[k] = 2.0 * s;
-        }
+        m += kept;
+        return false;
     }
-    ADC_HIP(hipStreamSynchronize(E.stream));
-    if (n_iter) *n_iter = it;
-    c->st_iters = it;
-    c->st_seconds = std::chrono::duration<double>(clk::now() - t0).count();
-    E.scratch.clear();    // also invalidates captured sigma graphs
-    return status;
+
+    bool end(int st) {
+        status = st;
+        done = true;
+        return true;
+    }
+
+    int finish(double* energies, double* P, double* vecs, int* n_iter) {
+        if (c->use_mlp && !use_mlp) c->mlp_fallbacks++;
+        for (int k = 0; k < nroots; ++k) energies[k] = theta[k];
+        if (vecs)
+            ADC_HIP(hipMemcpyAsync(vecs, d.X.p, (size_t)nroots * dim * sizeof(double),
+                                   hipMemcpyDeviceToDevice, E.stream));
+        if (P) {
+            DBuf<double> Xs;
+            Xs.alloc((size_t)nroots * c->N, &c->arena);
+            spec_amplitudes(c, d.X.p, nroots, Xs.p);
+            std::vector<double> xh((size_t)nroots * c->N);
+            ADC_HIP(hipMemcpyAsync(xh.data(), Xs.p, xh.size() * sizeof(double),
+                                   hipMemcpyDeviceToHost, E.stream));
+            ADC_HIP(hipStreamSynchronize(E.stream));
+            for (int k = 0; k < nroots; ++k) {
+                double s = 0.0;
+                for (int p = 0; p < c->N; ++p)
+                    s += xh[(size_t)k * c->N + p] * xh[(size_t)k * c->N + p];
+                P[k] = 2.0 * s;
+            }
+        }
+        ADC_HIP(hipStreamSynchronize(E.stream));
+        if (n_iter) *n_iter = it;
+        c->st_iters = it;
+        c->st_seconds = std::chrono::duration<double>(clk::now() - t0).count();
+        E.scratch.clear();    // also invalidates captured sigma graphs
+        return status;
+    }
+};
+
+Solver* solver_new(adc_ctx* c, int nroots) { return new Solver(c, nroots); }
+void solver_delete(Solver* s) { delete s; }
+bool solver_request(Solver* s, const double** X, double** W, int* nn, int* precision) {
+    return s->request(X, W, nn, precision);
+}
+bool solver_advance(Solver* s) { return s->advance(); }
+int solver_finish(Solver* s, double* energies, double* P, double* vecs, int* n_iter) {
+    return s->finish(energies, P, vecs, n_iter);
+}
+
+int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, int* n_iter) {
+    Solver s(c, nroots);
+    const double* X;
+    double* W;
+    int nn, precision;
+    while (s.request(&X, &W, &nn, &precision)) {
+        sigma(c, X, W, nn, precision);
+        s.advance();
+    }
+    return s.finish(energies, P, vecs, n_iter);
 }
 
 }  // namespace adc

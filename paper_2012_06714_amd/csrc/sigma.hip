@@ -266,7 +266,7 @@ void sigma_block(adc_ctx* c, const double* X, double* Yout, int nvec) {
     pair_transform<T, double>(E, S2, len2, 0, Yout, dim, n1, nvec, nx, np, AL, BE, beta2);
 }
 
-static void sigma_eager(adc_ctx* c, const double* X, double* Y, int nvec, int precision) {
+void sigma_eager(adc_ctx* c, const double* X, double* Y, int nvec, int precision) {
     if (precision == 1)
         sigma_block<float>(c, X, Y, nvec);
     else

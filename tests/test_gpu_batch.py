@@ -1,0 +1,70 @@
+"""Lockstep solves of several uneven systems (adc_batch_davidson) against the
+single-system solver on each: same sigma kernels, same solver steps, so the
+same roots and iteration counts."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _systems():
+    """Uneven systems of the batched EA-ADC(2) family (nocc capped at 10) plus
+    one EA-ADC(3) and one IP-ADC(3) system."""
+    from synthetic import make_batch_system, small_system
+    out = []
+    for s in (0, 1, 2):
+        eps, B, (O, V, Q) = make_batch_system(s, 10)
+        out.append((eps, B, O, 2, "ea"))
+    eps, B = small_system(4, 30, 70, 41)
+    out.append((eps, B, 4, 3, "ea"))
+    eps, B = small_system(6, 25, 60, 42)
+    out.append((eps, B, 6, 3, "ip"))
+    return out
+
+
+def _contexts(systems, precision=0):
+    import paper_2012_06714_amd as adc
+    dev = torch.device("cuda:0")
+    ctxs = []
+    for eps, B, O, order, kind in systems:
+        c = adc.Context(torch.tensor(eps, device=dev), torch.tensor(B, device=dev), O, order, kind)
+        c.set_option("tol_e", 1e-9)
+        c.set_option("tol_r", 1e-6)
+        c.set_option("block", 4)
+        c.set_option("precision", precision)
+        ctxs.append(c)
+    return ctxs
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_matches_single_solves(precision):
+    import paper_2012_06714_amd as adc
+    systems = _systems()
+    _say(f"case batch precision={precision}")
+    ref = []
+    for c in _contexts(systems, precision):
+        e, P, _, it, ok = c.davidson(3, want_vectors=False)
+        ref.append((np.array(e), np.array(P), it, ok))
+        c.close()
+    for use_graph in (True, False):
+        ctxs = _contexts(systems, precision)
+        e, P, it, st, stats = adc.batch_davidson(ctxs, 3, use_graph=use_graph)
+        for c in ctxs:
+            c.close()
+        _say(f"graph={use_graph} stats {stats} iterations {list(it)}")
+        for k, (e0, P0, it0, ok0) in enumerate(ref):
+            assert ok0 and st[k] == 0
+            assert it[k] == it0
+            assert np.abs(e[k] - e0).max() < 1e-10
+            assert (np.abs(P[k] - P0) / np.maximum(1, np.abs(P0))).max() < 1e-9
+        if use_graph:
+            assert stats["graph_launches"] == stats["iterations"]
+            assert 1 <= stats["captures"] <= stats["iterations"]
