@@ -23,6 +23,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAKS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+# HBM bytes per particle-particle launch (one sigma call) from two rocprofv3
+# counter runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, the factors of a plain
+# 1 GiB copy), summarised in profiles/pp_term_ea_adc3_o20v180_hbm_bytes.md.
+# Valid for the kernels as measured; re-measure whenever they change.
+PP_TRAFFIC = {("ea-adc3-o20v180", "fp64"): 5.108e10, ("ea-adc3-o20v180", "mixed"): 1.231e10}
 HBM_GBPS = 8000.0
 
 
@@ -58,6 +63,8 @@ def main():
     ap.add_argument("--no-davidson", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tune-log", action="store_true", help="log the GEMM autotuner's choices")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="end with a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -157,7 +164,7 @@ def main():
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAKS_TFLOPS[dtype_key],
                 "unit": "TFLOP/s",
                 "frac": (achieved / PEAKS_TFLOPS[dtype_key]) if achieved else None,
-                "traffic": None,
+                "traffic": PP_TRAFFIC.get((wl.name, precision)),
                 "kernel": "particle-particle term: (ac|bd) slab rebuild + contraction "
                           "(k_gemm kinds 1 and 2)",
                 "ms_per_launch": ms_pp, "flops_per_launch": f_pp}
@@ -193,6 +200,14 @@ def main():
     }
     out.update(extra)
     ctx.close()
+    if args.calib_copy:
+        # a plain copy of known size: 1 GiB read + 1 GiB written
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: calibration copy of 1 GiB done")
     print(json.dumps(out), flush=True)
     return 0
 

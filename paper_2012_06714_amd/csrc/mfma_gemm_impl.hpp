@@ -149,9 +149,14 @@ k_gemm(const TI* __restrict__ A, const TI* __restrict__ B, TO* __restrict__ C, G
     // regroup the linear id so that each XCD gets a contiguous run of tiles,
     // then walk that run in column groups of 8 row tiles (operand reuse in L2)
     const long long ntm = (g.M + BM - 1) / BM, ntn = (g.N + BN - 1) / BN;
+    // hardware id h goes to XCD h mod 8; XCD x takes the logical ids
+    // [x*q + min(x, r), ...) of length q + (x < r), q = nwg / 8, r = nwg mod 8
     long long pid = blockIdx.x;
     const long long nwg = (long long)gridDim.x;
-    if ((nwg & 7) == 0) pid = (pid & 7) * (nwg >> 3) + (pid >> 3);
+    {
+        const long long x = pid & 7, k = pid >> 3, q = nwg >> 3, r = nwg & 7;
+        pid = x * q + (x < r ? x : r) + k;
+    }
     const long long GROUP = 8;
     const long long per_group = GROUP * ntn;
     const long long grp = pid / per_group;
