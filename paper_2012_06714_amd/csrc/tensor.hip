@@ -259,26 +259,31 @@ void ctr(Engine& E, T alpha, const char* sa_, const T* A, const char* sb_, const
     for (char c : sb)
         if (has(sc, c) && !has(sa, c)) fb += c;
     // broadcast batching: leading free letters of an operand that also lead the
-    // output may be looped over as a batch with zero stride in the other operand
-    // (avoids permuting a large operand).
+    // output may be looped over as a batch with zero stride in the other operand.
+    // That is worth it only when it spares a permutation of that operand: else
+    // the letters stay in the GEMM's M (or N), which gives larger tiles and
+    // reads the other operand once per tile row instead of once per batch item.
     auto prefix_len = [](const std::string& x, const std::string& y) {
         size_t n = 0;
         while (n < x.size() && n < y.size() && x[n] == y[n]) ++n;
         return n;
     };
+    auto usable = [&](const std::string& op, const std::string& lead, const std::string& f,
+                      const std::string& k) { return op == lead + f + k || op == lead + k + f; };
     if (batch.empty()) {
         size_t nb = prefix_len(sb, sc);
-        // only letters that are free in B
         size_t k = 0;
-        while (k < nb && has(fb, sb[k])) ++k;
-        if (k > 0 && k < fb.size()) {
+        while (k < nb && has(fb, sb[k])) ++k;    // only letters that are free in B
+        if (k > 0 && k < fb.size() && usable(sb, sb.substr(0, k), fb.substr(k), contr) &&
+            !usable(sb, "", fb, contr)) {
             bcastB = sb.substr(0, k);
             fb = fb.substr(k);
         } else {
             size_t na = prefix_len(sa, sc);
             k = 0;
             while (k < na && has(fa, sa[k])) ++k;
-            if (k > 0 && k < fa.size()) {
+            if (k > 0 && k < fa.size() && usable(sa, sa.substr(0, k), fa.substr(k), contr) &&
+                !usable(sa, "", fa, contr)) {
                 bcastA = sa.substr(0, k);
                 fa = fa.substr(k);
             }
