@@ -12,8 +12,10 @@
 //            relative for roots beyond 1 Eh, absolute otherwise);
 //   correction d = r / (theta - D) with |theta - D| floored at 1e-8, or the
 //            learned correction of it (mlp.hip) when a network is installed;
-//   each new direction is orthogonalised twice against V and the directions
-//   already accepted, and dropped if its norm falls below 1e-10;
+//   new directions (scaled to unit norm) are orthogonalised against V by block
+//            Gram-Schmidt and among themselves through their Gram matrix, in
+//            two passes; directions whose Gram eigenvalue falls below
+//            max(1e-20, 1e-14 lambda_max) are dropped;
 //   restart to the current `block` Ritz vectors when V would exceed max_space.
 // Mixed precision ("precision" = 1): sigma runs in reduced precision until the
 // (scaled) residuals fall below max(sqrt(tol_r), 1e-3) or 3e-3, or stop
@@ -139,12 +141,13 @@ struct Dav {
         ADC_HIP(hipStreamSynchronize(E.stream));
     }
 
-    // orthonormalise nd rows of Dm against V[0:m] and among themselves: the rows
-    // are scaled to unit norm, projected out of V by two block classical
-    // Gram-Schmidt passes (one long-K GEMM each way), then taken one at a time
-    // against the rows already accepted (two passes); rows whose norm falls
-    // below 1e-10 are dropped, the rest normalised and compacted to the front.
-    // Returns the number kept.
+    // orthonormalise nd rows of Dm against V[0:m] and among themselves.  Two
+    // passes of: block classical Gram-Schmidt against V (one long-K GEMM each
+    // way), then the block's own Gram matrix G = Dm Dm^T, diagonalised on the
+    // host (nd is small), and Dm <- L^-1/2 U^T Dm over the eigenpairs with
+    // lambda > max(1e-20, 1e-14 lambda_max): directions that fall below (rows
+    // of unit norm that are numerically dependent on V or on each other) are
+    // dropped.  The kept rows are compacted to the front; returns their count.
     int orthonormalize(double* Dm, int nd, int m) {
         cmat.alloc((size_t)std::max(1, nd * std::max(m, nd)), &c->arena);
         std::vector<double> nrm;
@@ -155,39 +158,95 @@ struct Dav {
                                Dm + (size_t)k * dim, s, dim);
         }
         ADC_HIP(hipGetLastError());
-        if (m > 0) {
-            for (int pass = 0; pass < 2; ++pass) {
-                gemm_rm<double>(E, false, true, nd, m, dim, 1.0, Dm, dim, 0, V.p, dim, 0, 0.0,
-                                cmat.p, m, 0, 1);
-                gemm_rm<double>(E, false, false, nd, dim, m, -1.0, cmat.p, m, 0, V.p, dim, 0, 1.0,
-                                Dm, dim, 0, 1);
-            }
-        }
-        int kept = 0;
-        for (int k = 0; k < nd; ++k) {
-            double* dk = Dm + (size_t)k * dim;
-            double* out = Dm + (size_t)kept * dim;
-            if (k != kept)
-                ADC_HIP(hipMemcpyAsync(out, dk, dim * sizeof(double), hipMemcpyDeviceToDevice,
-                                       E.stream));
-            if (kept > 0) {
-                for (int pass = 0; pass < 2; ++pass) {
-                    gemm_rm<double>(E, false, true, 1, kept, dim, 1.0, out, dim, 0, Dm, dim, 0, 0.0,
-                                    cmat.p, kept, 0, 1);
-                    gemm_rm<double>(E, false, false, 1, dim, kept, -1.0, cmat.p, kept, 0, Dm, dim,
-                                    0, 1.0, out, dim, 0, 1);
+        DBuf<double> tmp;
+        tmp.alloc((size_t)nd * dim, &c->arena);
+        std::vector<double> G, T;
+        for (int pass = 0; pass < 2 && nd > 0; ++pass) {
+            if (m > 0) {
+                for (int cgs = 0; cgs < 2; ++cgs) {
+                    gemm_rm<double>(E, false, true, nd, m, dim, 1.0, Dm, dim, 0, V.p, dim, 0, 0.0,
+                                    cmat.p, m, 0, 1);
+                    gemm_rm<double>(E, false, false, nd, dim, m, -1.0, cmat.p, m, 0, V.p, dim, 0,
+                                    1.0, Dm, dim, 0, 1);
                 }
             }
-            rownorms(out, 1, nrm);
-            if (nrm[0] > 1e-10 && std::isfinite(nrm[0])) {
-                hipLaunchKernelGGL(k_scale, dim3(nb_(dim)), dim3(256), 0, E.stream, out,
-                                   1.0 / nrm[0], dim);
-                ADC_HIP(hipGetLastError());
+            gemm_rm<double>(E, false, true, nd, nd, dim, 1.0, Dm, dim, 0, Dm, dim, 0, 0.0, cmat.p,
+                            nd, 0, 1);
+            G.resize((size_t)nd * nd);
+            ADC_HIP(hipMemcpyAsync(G.data(), cmat.p, G.size() * sizeof(double),
+                                   hipMemcpyDeviceToHost, E.stream));
+            ADC_HIP(hipStreamSynchronize(E.stream));
+            for (int i = 0; i < nd; ++i)
+                for (int j = 0; j < i; ++j) {
+                    double v = 0.5 * (G[(size_t)i * nd + j] + G[(size_t)j * nd + i]);
+                    G[(size_t)i * nd + j] = G[(size_t)j * nd + i] = v;
+                }
+            std::vector<double> lam, U;
+            jacobi_eigen(G, nd, lam, U);
+            double lmax = 0.0;
+            for (double l : lam) lmax = std::max(lmax, l);
+            const double cut = std::max(1e-20, 1e-14 * lmax);
+            T.clear();
+            int kept = 0;
+            for (int k = 0; k < nd; ++k) {
+                if (!(lam[k] > cut) || !std::isfinite(lam[k])) continue;
+                const double f = 1.0 / std::sqrt(lam[k]);
+                for (int j = 0; j < nd; ++j) T.push_back(U[(size_t)j * nd + k] * f);
                 ++kept;
             }
+            if (kept == 0) return 0;
+            ADC_HIP(hipMemcpyAsync(cmat.p, T.data(), T.size() * sizeof(double),
+                                   hipMemcpyHostToDevice, E.stream));
+            gemm_rm<double>(E, false, false, kept, dim, nd, 1.0, cmat.p, nd, 0, Dm, dim, 0, 0.0,
+                            tmp.p, dim, 0, 1);
+            ADC_HIP(hipMemcpyAsync(Dm, tmp.p, (size_t)kept * dim * sizeof(double),
+                                   hipMemcpyDeviceToDevice, E.stream));
+            nd = kept;
         }
         ADC_HIP(hipStreamSynchronize(E.stream));
-        return kept;
+        return nd;
+    }
+
+    // eigenpairs of a small symmetric matrix (cyclic Jacobi rotations):
+    // lam[k], U[j][k] = component j of eigenvector k
+    static void jacobi_eigen(std::vector<double> A, int n, std::vector<double>& lam,
+                             std::vector<double>& U) {
+        U.assign((size_t)n * n, 0.0);
+        for (int i = 0; i < n; ++i) U[(size_t)i * n + i] = 1.0;
+        for (int sweep = 0; sweep < 100; ++sweep) {
+            double off = 0.0, diag = 0.0;
+            for (int i = 0; i < n; ++i) {
+                diag += A[(size_t)i * n + i] * A[(size_t)i * n + i];
+                for (int j = i + 1; j < n; ++j) off += A[(size_t)i * n + j] * A[(size_t)i * n + j];
+            }
+            if (off <= 1e-32 * diag || off == 0.0) break;
+            for (int p = 0; p < n; ++p)
+                for (int q = p + 1; q < n; ++q) {
+                    const double apq = A[(size_t)p * n + q];
+                    if (apq == 0.0) continue;
+                    const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+                    const double th = 0.5 * (aqq - app) / apq;
+                    const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                    const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+                    for (int k = 0; k < n; ++k) {
+                        const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+                        A[(size_t)k * n + p] = cs * akp - sn * akq;
+                        A[(size_t)k * n + q] = sn * akp + cs * akq;
+                    }
+                    for (int k = 0; k < n; ++k) {
+                        const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+                        A[(size_t)p * n + k] = cs * apk - sn * aqk;
+                        A[(size_t)q * n + k] = sn * apk + cs * aqk;
+                    }
+                    for (int k = 0; k < n; ++k) {
+                        const double ukp = U[(size_t)k * n + p], ukq = U[(size_t)k * n + q];
+                        U[(size_t)k * n + p] = cs * ukp - sn * ukq;
+                        U[(size_t)k * n + q] = sn * ukp + cs * ukq;
+                    }
+                }
+        }
+        lam.resize(n);
+        for (int i = 0; i < n; ++i) lam[i] = A[(size_t)i * n + i];
     }
 };
 
