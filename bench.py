@@ -63,6 +63,7 @@ def main():
     ap.add_argument("--no-davidson", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tune-log", action="store_true", help="log the GEMM autotuner's choices")
+    ap.add_argument("--verbose", action="store_true", help="per-iteration solver lines on stderr")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -93,6 +94,8 @@ def main():
     log(f"bench: setup {t_setup:.2f} s, dim {ctx.dim}")
     if args.tune_log:
         ctx.set_option("autotune", 2)
+    if args.verbose:
+        ctx.set_option("verbose", 1)
 
     nvec = wl.block
     X = torch.tensor(random_vectors(ctx.dim, nvec, 11), device=dev)
