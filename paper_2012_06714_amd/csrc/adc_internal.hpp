@@ -161,6 +161,7 @@ struct Engine {
     std::map<std::array<long long, 12>, int> tuned;
     hipEvent_t tev[2] = {nullptr, nullptr};
     bool timing = false;     // record events around the particle-particle kernels
+    bool ctr_log = false;    // time every contraction and print its GEMM plan to stderr
     double pp_ms = 0.0;      // accumulated milliseconds of those kernels
 };
 

@@ -127,6 +127,10 @@ int adc_set_option(adc_ctx* c, const char* key, double value) {
         if (value != 0 && value != 1 && value != 2) return fail(c, ADC_E_ARG, "autotune: 0, 1 or 2");
         c->E.autotune = value != 0;
         c->E.tune_log = value == 2;
+    } else if (k == "ctr_log") {
+        // 1: time each contraction of sigma with events and print its plan on stderr
+        if (value != 0 && value != 1) return fail(c, ADC_E_ARG, "ctr_log: 0 or 1");
+        c->E.ctr_log = value == 1;
     } else if (k == "pp_slab_mb") {
         if (value < 1 || value > 1048576) return fail(c, ADC_E_ARG, "pp_slab_mb out of range");
         c->pp_slab_bytes = (long long)(value * 1048576.0);

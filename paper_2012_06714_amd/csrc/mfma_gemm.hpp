@@ -27,9 +27,18 @@ struct GemmOut {
     }
 };
 
+// Two-level batches: batch index z = z1 * n + z2 (z2 fastest, z < batch * n);
+// the operands and the result advance by the outer strides (sA, sB, sC) per z1
+// and by these inner strides per z2.  Split-K runs its k-chunks as the inner
+// level.
+struct GemmInner {
+    long long n = 1, sA = 0, sB = 0, sC = 0;
+};
+
 struct GemmShape {
     long long M, N, K, lda, ldb, sA, sB, sC;
     long long rsplit, rs1, rs2, csplit, cs1, cs2;
+    long long n2, sA2, sB2, sC2, z0;
     bool vecA, vecB;
 };
 
@@ -44,7 +53,7 @@ template <typename TI, typename T, typename TO>
 void mfma_gemm(hipStream_t st, bool ta, bool tb, long long M, long long N, long long K,
                typename AccOf<T>::type alpha, const TI* A, long long lda, long long sA, const TI* B,
                long long ldb, long long sB, typename AccOf<T>::type beta, TO* C, GemmOut out,
-               long long batch, int kind = 0, int cfg = -1);
+               long long batch, int kind = 0, int cfg = -1, GemmInner inner = GemmInner());
 
 // Tile configurations compiled for compute type T (ids as in gemm_tile_dims);
 // returns the count written to ids[] (at most 8).
@@ -58,7 +67,7 @@ template <typename TI, typename T, typename TO>
 void gemm_run(Engine& E, bool ta, bool tb, long long M, long long N, long long K,
               typename AccOf<T>::type alpha, const TI* A, long long lda, long long sA,
               const TI* B, long long ldb, long long sB, typename AccOf<T>::type beta, TO* C,
-              GemmOut out, long long batch, int kind = 0);
+              GemmOut out, long long batch, int kind = 0, GemmInner inner = GemmInner());
 // kind only names the kernel in profiles: 0 plain, 1 four-index rebuild,
 // 2 particle-particle contraction (1 and 2 are NT only)
 

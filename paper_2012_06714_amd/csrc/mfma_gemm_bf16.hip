@@ -7,7 +7,7 @@ namespace adc {
     template void mfma_gemm<TI, T, TO>(hipStream_t, bool, bool, long long, long long, long long, \
                                        AccOf<T>::type, const TI*, long long, long long, const TI*, \
                                        long long, long long, AccOf<T>::type, TO*, GemmOut,       \
-                                       long long, int, int);
+                                       long long, int, int, GemmInner);
 ADC_INST(float, bf16_t, float)
 ADC_INST(bf16_t, bf16_t, float)
 ADC_INST(bf16_t, bf16_t, bf16_t)

@@ -166,10 +166,13 @@ k_gemm(const TI* __restrict__ A, const TI* __restrict__ B, TO* __restrict__ C, G
     const long long tni = (pid % per_group) / gsz;
     const long long m0 = tmi * BM, n0 = tni * BN;
 
-    const long long bz = blockIdx.z;
-    A += bz * g.sA;
-    B += bz * g.sB;
-    C += bz * g.sC;
+    {
+        const long long bz = g.z0 + blockIdx.z;
+        const long long b1 = bz / g.n2, b2 = bz - b1 * g.n2;
+        A += b1 * g.sA + b2 * g.sA2;
+        B += b1 * g.sB + b2 * g.sB2;
+        C += b1 * g.sC + b2 * g.sC2;
+    }
 
     // ---- global -> register staging ------------------------------------
     // A chunk is 16 bytes of compute-type elements: VW consecutive k of one
@@ -180,19 +183,28 @@ k_gemm(const TI* __restrict__ A, const TI* __restrict__ B, TO* __restrict__ C, G
                   "tile does not split into 16-byte chunks per thread");
     uint4 ra[CA], rb[CB];
 
-    // unguarded 16-byte loads (interior tiles, aligned rows, full k-tile)
-    auto load_fast = [&](const TI* P, long long ld, auto trans_tag, long long R0, int R, uint4* r,
-                         int nchunk, long long k0) {
+    // 16-byte loads of a full k-tile (k0 + BK <= K) of an aligned operand.
+    // Rows past the operand's extent only feed output rows (columns) that the
+    // epilogue discards, so their addresses are clamped into the operand
+    // instead of being checked: a [row][k] source reads its last row again, a
+    // [k][row] source (ld a multiple of VW) reads the last VW entries of the
+    // k-row.  Any tile of the grid runs this path.
+    auto load_fast = [&](const TI* P, long long ld, auto trans_tag, long long R0, long long Rmax,
+                         int R, uint4* r, int nchunk, long long k0) {
         constexpr bool TR = decltype(trans_tag)::value;
 #pragma unroll
         for (int c = 0; c < nchunk; ++c) {
             const int id = tid + c * NT;
             if constexpr (!TR) {
-                const int row = id / (BK / VW), kc = (id % (BK / VW)) * VW;
-                r[c] = Chunk<TI, T>::vec(P + (R0 + row) * ld + k0 + kc);
+                long long row = R0 + id / (BK / VW);
+                row = row < Rmax ? row : Rmax - 1;
+                const int kc = (id % (BK / VW)) * VW;
+                r[c] = Chunk<TI, T>::vec(P + row * ld + k0 + kc);
             } else {
-                const int kk = id / (R / VW), rc = (id % (R / VW)) * VW;
-                r[c] = Chunk<TI, T>::vec(P + (k0 + kk) * ld + R0 + rc);
+                const int kk = id / (R / VW);
+                long long col = R0 + (id % (R / VW)) * VW;
+                col = col <= ld - VW ? col : ld - VW;
+                r[c] = Chunk<TI, T>::vec(P + (k0 + kk) * ld + col);
             }
         }
     };
@@ -318,15 +330,14 @@ k_gemm(const TI* __restrict__ A, const TI* __restrict__ B, TO* __restrict__ C, G
         }
     };
 
-    // k-tiles that need no bounds checks: all full tiles of an interior,
-    // vector-aligned block; the rest (ragged k tail, edge blocks) are guarded
+    // k-tiles that need no bounds checks: every full tile when both operands
+    // are vector-aligned; the ragged k tail (and unaligned operands) are guarded
     const long long nk = (g.K + BK - 1) / BK;
-    const bool interior = g.vecA && g.vecB && m0 + BM <= g.M && n0 + BN <= g.N;
-    const long long nfast = interior ? g.K / BK : 0;
+    const long long nfast = (g.vecA && g.vecB) ? g.K / BK : 0;
     if (nk > 0) {
         if (nfast > 0) {
-            load_fast(A, g.lda, TrA{}, m0, BM, ra, CA, 0);
-            load_fast(B, g.ldb, TrB{}, n0, BN, rb, CB, 0);
+            load_fast(A, g.lda, TrA{}, m0, g.M, BM, ra, CA, 0);
+            load_fast(B, g.ldb, TrB{}, n0, g.N, BN, rb, CB, 0);
         } else {
             load_safe(A, g.lda, TrA{}, m0, g.M, BM, ra, CA, 0);
             load_safe(B, g.ldb, TrB{}, n0, g.N, BN, rb, CB, 0);
@@ -338,8 +349,8 @@ k_gemm(const TI* __restrict__ A, const TI* __restrict__ B, TO* __restrict__ C, G
         // the next tile is a fast one
         for (; kt + 1 < nfast; ++kt) {
             const int cur = kt & 1;
-            load_fast(A, g.lda, TrA{}, m0, BM, ra, CA, (kt + 1) * BK);
-            load_fast(B, g.ldb, TrB{}, n0, BN, rb, CB, (kt + 1) * BK);
+            load_fast(A, g.lda, TrA{}, m0, g.M, BM, ra, CA, (kt + 1) * BK);
+            load_fast(B, g.ldb, TrB{}, n0, g.N, BN, rb, CB, (kt + 1) * BK);
             compute(cur);
             store(sA[cur ^ 1], TrA{}, BM, ra, CA);
             store(sB[cur ^ 1], TrB{}, BN, rb, CB);
@@ -395,22 +406,21 @@ static void launch_tiles(hipStream_t st, bool ta, bool tb, const TI* A, const TI
     // the batch index runs over grid z (at most 65535 per launch)
     for (long long z0 = 0; z0 < batch; z0 += 65535) {
         const long long nz = std::min<long long>(65535, batch - z0);
-        const TI* Az = A + z0 * g.sA;
-        const TI* Bz = B + z0 * g.sB;
-        TO* Cz = C + z0 * g.sC;
+        GemmShape gz = g;
+        gz.z0 = z0;
         dim3 grid((unsigned)(ntm * ntn), 1, (unsigned)nz);
         if (KIND != 0 || (!ta && tb))
             hipLaunchKernelGGL((k_gemm<TI, T, TO, BM, BN, WGM, WGN, false, true, KIND>), grid,
-                               dim3(NT), 0, st, Az, Bz, Cz, g, alpha, beta);
+                               dim3(NT), 0, st, A, B, C, gz, alpha, beta);
         else if (!ta && !tb)
             hipLaunchKernelGGL((k_gemm<TI, T, TO, BM, BN, WGM, WGN, false, false, 0>), grid,
-                               dim3(NT), 0, st, Az, Bz, Cz, g, alpha, beta);
+                               dim3(NT), 0, st, A, B, C, gz, alpha, beta);
         else if (ta && !tb)
             hipLaunchKernelGGL((k_gemm<TI, T, TO, BM, BN, WGM, WGN, true, false, 0>), grid,
-                               dim3(NT), 0, st, Az, Bz, Cz, g, alpha, beta);
+                               dim3(NT), 0, st, A, B, C, gz, alpha, beta);
         else
             hipLaunchKernelGGL((k_gemm<TI, T, TO, BM, BN, WGM, WGN, true, true, 0>), grid,
-                               dim3(NT), 0, st, Az, Bz, Cz, g, alpha, beta);
+                               dim3(NT), 0, st, A, B, C, gz, alpha, beta);
         ADC_HIP(hipGetLastError());
     }
 }
@@ -441,8 +451,9 @@ template <typename TI, typename T, typename TO>
 void mfma_gemm(hipStream_t st, bool ta, bool tb, long long M, long long N, long long K,
                typename AccOf<T>::type alpha, const TI* A, long long lda, long long sA, const TI* B,
                long long ldb, long long sB, typename AccOf<T>::type beta, TO* C, GemmOut out,
-               long long batch, int kind, int cfg_req) {
-    if (M <= 0 || N <= 0 || batch <= 0) return;
+               long long batch, int kind, int cfg_req, GemmInner inner) {
+    if (M <= 0 || N <= 0 || batch <= 0 || inner.n <= 0) return;
+    ADC_REQUIRE(inner.n == 1 || batch * inner.n <= 65535, "gemm: two-level batch too large");
     ADC_REQUIRE(kind == 0 || (!ta && tb), "gemm: tagged kernels are NT only");
     ADC_REQUIRE(K >= 0 && lda >= (ta ? M : K) && ldb >= (tb ? K : N), "gemm: leading dimension");
     ADC_REQUIRE(A && B && C, "gemm: null operand");
@@ -461,9 +472,22 @@ void mfma_gemm(hipStream_t st, bool ta, bool tb, long long M, long long N, long 
     g.csplit = out.csplit > 0 ? out.csplit : N;
     g.cs1 = out.cs1;
     g.cs2 = out.cs2;
-    constexpr int VW = 16 / sizeof(T);
-    g.vecA = aligned16(A) && (lda % VW == 0) && (batch == 1 || sA % VW == 0);
-    g.vecB = aligned16(B) && (ldb % VW == 0) && (batch == 1 || sB % VW == 0);
+    g.n2 = inner.n;
+    g.sA2 = inner.sA;
+    g.sB2 = inner.sB;
+    g.sC2 = inner.sC;
+    g.z0 = 0;
+    // the two levels run as one flat batch over grid z
+    batch *= inner.n;
+    // 16-byte loads: every offset a multiple of VWI storage elements; a
+    // [k][row] operand also needs whole VW-element chunks per k-row (the
+    // clamp of rows past the extent relies on it)
+    constexpr int VW = 16 / sizeof(T), VWI = 16 / sizeof(TI);
+    const bool rowsA = ta, rowsB = !tb;     // [k][row] layouts
+    g.vecA = aligned16(A) && (lda % (rowsA ? VW : VWI) == 0) && (batch == 1 || sA % VWI == 0) &&
+             inner.sA % VWI == 0;
+    g.vecB = aligned16(B) && (ldb % (rowsB ? VW : VWI) == 0) && (batch == 1 || sB % VWI == 0) &&
+             inner.sB % VWI == 0;
     if (K <= 0) {
         // nothing to accumulate: C = beta C through the same epilogue
         g.K = 0;

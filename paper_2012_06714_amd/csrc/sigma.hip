@@ -372,7 +372,7 @@ void sigma(adc_ctx* c, const double* X, double* Y, int nvec, int precision) {
         int nz = nvec - z0 < chunk ? nvec - z0 : chunk;
         const double* Xz = X + (long long)z0 * c->dim;
         double* Yz = Y + (long long)z0 * c->dim;
-        if (c->use_graph && !c->E.timing)
+        if (c->use_graph && !c->E.timing && !c->E.ctr_log)
             sigma_graph(c, Xz, Yz, nz, precision);
         else
             sigma_eager(c, Xz, Yz, nz, precision);

@@ -87,29 +87,32 @@ template <typename TI, typename T, typename TO>
 void gemm_run(Engine& E, bool ta, bool tb, long long M, long long N, long long K,
               typename AccOf<T>::type alpha, const TI* A, long long lda, long long sA,
               const TI* B, long long ldb, long long sB, typename AccOf<T>::type beta, TO* C,
-              GemmOut out, long long batch, int kind) {
+              GemmOut out, long long batch, int kind, GemmInner inner) {
     using Acc = typename AccOf<T>::type;
-    if (M <= 0 || N <= 0 || batch <= 0) return;
+    if (M <= 0 || N <= 0 || batch <= 0 || inner.n <= 0) return;
     const std::array<long long, 12> key{(long long)sizeof(TI), (long long)sizeof(T),
-                                        (long long)sizeof(TO), ta, tb, M, N, K, batch, kind,
-                                        out.rsplit > 0, out.csplit > 0};
+                                        (long long)sizeof(TO), ta, tb, M, N, K, batch * inner.n,
+                                        kind, out.rsplit > 0, out.csplit > 0};
     auto it = E.tuned.find(key);
     if (it != E.tuned.end()) {
         mfma_gemm<TI, T, TO>(E.stream, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,
-                             out, batch, kind, it->second);
+                             out, batch, kind, it->second, inner);
         return;
     }
-    const double flops = 2.0 * M * N * K * batch;
-    const size_t cbytes = sizeof(TO) * (size_t)M * N * batch;
-    if (!E.autotune || flops < 2e8 || (beta != Acc(0) && cbytes > (size_t(512) << 20))) {
+    const double flops = 2.0 * M * N * K * batch * inner.n;
+    const size_t cbytes = sizeof(TO) * (size_t)M * N * batch * inner.n;
+    // trials of a two-level batch would need a scratch copy of its whole
+    // strided output: those shapes take the heuristic choice
+    if (!E.autotune || flops < 2e8 || (beta != Acc(0) && (cbytes > (size_t(512) << 20) || inner.n > 1))) {
         mfma_gemm<TI, T, TO>(E.stream, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,
-                             out, batch, kind, -1);
+                             out, batch, kind, -1, inner);
         return;
     }
     // trials: in place when the product overwrites C, else on a scratch output
     TO* Ct = C;
     GemmOut ot = out;
     Acc bt = beta;
+    GemmInner it2 = inner;
     if (beta != Acc(0)) {
         Ct = (TO*)E.scratch.get(28, cbytes);
         ot = GemmOut::rowmajor(N, M * N);
@@ -126,7 +129,7 @@ void gemm_run(Engine& E, bool ta, bool tb, long long M, long long N, long long K
     for (int k = 0; k < n; ++k) {
         ADC_HIP(hipEventRecord(E.tev[0], E.stream));
         mfma_gemm<TI, T, TO>(E.stream, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, bt, Ct, ot,
-                             batch, kind, ids[k]);
+                             batch, kind, ids[k], it2);
         ADC_HIP(hipEventRecord(E.tev[1], E.stream));
         ADC_HIP(hipEventSynchronize(E.tev[1]));
         float ms = 0.f;
@@ -141,17 +144,17 @@ void gemm_run(Engine& E, bool ta, bool tb, long long M, long long N, long long K
         fprintf(stderr, "gemm tune: in %d B cmp %d B out %d B %c%c M %lld N %lld K %lld batch %lld "
                 "kind %d -> config %d (%.3f ms, %.1f TFLOP/s)\n",
                 (int)sizeof(TI), (int)sizeof(T), (int)sizeof(TO), ta ? 'T' : 'N', tb ? 'T' : 'N',
-                M, N, K, batch, kind, bc, best, flops / (best * 1e-3) / 1e12);
+                M, N, K, batch * inner.n, kind, bc, best, flops / (best * 1e-3) / 1e12);
     if (Ct != C)
         mfma_gemm<TI, T, TO>(E.stream, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,
-                             out, batch, kind, bc);
+                             out, batch, kind, bc, inner);
 }
 
 #define ADC_RUN_INST(TI, T, TO)                                                                  \
     template void gemm_run<TI, T, TO>(Engine&, bool, bool, long long, long long, long long,      \
                                       AccOf<T>::type, const TI*, long long, long long, const TI*, \
                                       long long, long long, AccOf<T>::type, TO*, GemmOut,         \
-                                      long long, int);
+                                      long long, int, GemmInner);
 ADC_RUN_INST(double, double, double)
 ADC_RUN_INST(float, float, float)
 ADC_RUN_INST(float, bf16_t, float)
@@ -160,20 +163,36 @@ ADC_RUN_INST(bf16_t, bf16_t, bf16_t)
 #undef ADC_RUN_INST
 
 // Skinny products with a long summed index (Davidson overlaps, gemv-like
-// contractions) would leave most of the chip idle: split K into chunks run as
-// one batched GEMM into partial results, then reduce them in a fixed order.
+// contractions, small batched products) would leave most of the chip idle:
+// split K into chunks run as the inner level of a two-level batched GEMM
+// into partial results [chunk][batch][M][N], then reduce them in a fixed order.
 template <typename A>
-__global__ void k_splitk_reduce(const A* __restrict__ part, int S, long long M, long long N,
-                                A* __restrict__ C, long long ldc, A beta) {
-    const long long MN = M * N;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < MN;
+__global__ void k_splitk_reduce(const A* __restrict__ part, int S, long long batch, long long M,
+                                long long N, A* __restrict__ C, long long ldc, long long sC,
+                                A beta) {
+    const long long MN = M * N, tot = batch * MN;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
          e += (long long)gridDim.x * blockDim.x) {
         A v = 0;
-        for (int s = 0; s < S; ++s) v += part[s * MN + e];
-        const long long m = e / N, n = e - m * N;
-        A* o = C + m * ldc + n;
+        for (int s = 0; s < S; ++s) v += part[s * tot + e];
+        const long long b = e / MN, r = e - b * MN;
+        const long long m = r / N, n = r - m * N;
+        A* o = C + b * sC + m * ldc + n;
         *o = (beta == A(0)) ? v : beta * *o + v;
     }
+}
+
+// number of k-chunks for a product of `wgs` 64x64 workgroups: enough chunks
+// to give the chip about 1024 workgroups, each chunk at least 512 long, the
+// partial results at most 256 MiB
+static long long splitk_chunks(long long M, long long N, long long K, long long batch, size_t acc) {
+    const long long wgs = ((M + 63) / 64) * ((N + 63) / 64) * batch;
+    if (wgs >= 256 || K < 1024) return 1;
+    long long S = std::min<long long>((1024 + wgs - 1) / wgs, K / 512);
+    S = std::min<long long>(S, 65535 / batch);
+    const long long cap = (long long)((size_t(256) << 20) / (acc * (size_t)(M * N * batch)));
+    S = std::min(S, cap);
+    return std::max<long long>(S, 1);
 }
 
 template <typename TI, typename T>
@@ -182,29 +201,36 @@ static void gemm_any(Engine& E, bool ta, bool tb, long long M, long long N, long
                      long long sB, TI beta, TI* C, long long ldc, long long sC, long long batch) {
     using Acc = typename AccOf<T>::type;
     static_assert(sizeof(Acc) == sizeof(TI), "accumulator must match the output type");
-    const long long tiles = ((M + 63) / 64) * ((N + 63) / 64) * batch;
-    if (batch == 1 && tiles < 64 && K >= 16384) {
-        long long S = std::min<long long>(K / 8192, 512 / tiles);
-        if (S >= 2) {
-            long long Kc = (K + S - 1) / S;
-            Kc = (Kc + 63) / 64 * 64;
-            S = (K + Kc - 1) / Kc;
-            const long long Klast = K - (S - 1) * Kc;
-            Acc* part = (Acc*)E.scratch.get(31, sizeof(Acc) * S * M * N);
-            const long long offA = ta ? Kc * lda : Kc, offB = tb ? Kc : Kc * ldb;
-            if (S > 1)
-                gemm_run<TI, T, Acc>(E, ta, tb, M, N, Kc, (Acc)alpha, A, lda, offA, B, ldb, offB,
-                                     Acc(0), part, GemmOut::rowmajor(N, M * N), S - 1);
-            gemm_run<TI, T, Acc>(E, ta, tb, M, N, Klast, (Acc)alpha, A + (S - 1) * offA, lda, 0,
-                                 B + (S - 1) * offB, ldb, 0, Acc(0), part + (S - 1) * M * N,
-                                 GemmOut::rowmajor(N), 1);
-            long long g = (M * N + 255) / 256;
-            if (g > 4096) g = 4096;
-            hipLaunchKernelGGL(k_splitk_reduce<Acc>, dim3((unsigned)g), dim3(256), 0, E.stream,
-                               part, (int)S, M, N, (Acc*)C, ldc, (Acc)beta);
-            ADC_HIP(hipGetLastError());
-            return;
-        }
+    long long S = splitk_chunks(M, N, K, batch, sizeof(Acc));
+    long long Kc = K;
+    if (S >= 2) {
+        Kc = (K + S - 1) / S;
+        Kc = (Kc + 63) / 64 * 64;
+        S = (K + Kc - 1) / Kc;
+    }
+    if (S >= 2) {
+        const long long Klast = K - (S - 1) * Kc;
+        const long long MNB = M * N * batch;
+        Acc* part = (Acc*)E.scratch.get(31, sizeof(Acc) * S * MNB);
+        // k offsets of one chunk in A and B
+        const long long offA = ta ? Kc * lda : Kc, offB = tb ? Kc : Kc * ldb;
+        GemmInner in;
+        in.n = S - 1;
+        in.sA = offA;
+        in.sB = offB;
+        in.sC = MNB;
+        // chunks 0 .. S-2 (inner level) of every batch item (outer level)
+        gemm_run<TI, T, Acc>(E, ta, tb, M, N, Kc, (Acc)alpha, A, lda, sA, B, ldb, sB, Acc(0), part,
+                             GemmOut::rowmajor(N, M * N), batch, 0, in);
+        gemm_run<TI, T, Acc>(E, ta, tb, M, N, Klast, (Acc)alpha, A + (S - 1) * offA, lda, sA,
+                             B + (S - 1) * offB, ldb, sB, Acc(0), part + (S - 1) * MNB,
+                             GemmOut::rowmajor(N, M * N), batch);
+        long long g = (MNB + 255) / 256;
+        if (g > 4096) g = 4096;
+        hipLaunchKernelGGL(k_splitk_reduce<Acc>, dim3((unsigned)g), dim3(256), 0, E.stream, part,
+                           (int)S, batch, M, N, (Acc*)C, ldc, sC, (Acc)beta);
+        ADC_HIP(hipGetLastError());
+        return;
     }
     gemm_run<TI, T, TI>(E, ta, tb, M, N, K, (Acc)alpha, A, lda, sA, B, ldb, sB, (Acc)beta, C,
                         GemmOut::rowmajor(ldc, sC), batch);
@@ -299,6 +325,43 @@ void ctr(Engine& E, T alpha, const char* sa_, const T* A, const char* sb_, const
     long long M = ext(fa), N = ext(fb), K = ext(contr);
     if (nbatch == 0 || M == 0 || N == 0) return;
 
+    struct Log {
+        Engine& e;
+        hipEvent_t a = nullptr, b = nullptr;
+        std::string text;
+        double flops = 0;
+        explicit Log(Engine& en) : e(en) {
+            if (!e.ctr_log) return;
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            ADC_HIP(hipStreamIsCapturing(e.stream, &cs));
+            if (cs != hipStreamCaptureStatusNone) return;    // no timing inside a capture
+            ADC_HIP(hipEventCreate(&a));
+            ADC_HIP(hipEventCreate(&b));
+        }
+        void start() { if (a) ADC_HIP(hipEventRecord(a, e.stream)); }
+        ~Log() {
+            if (!a) return;
+            float ms = 0.f;
+            if (hipEventRecord(b, e.stream) == hipSuccess && hipEventSynchronize(b) == hipSuccess)
+                (void)hipEventElapsedTime(&ms, a, b);
+            fprintf(stderr, "ctr %s: %.3f ms %.1f TFLOP/s\n", text.c_str(), ms,
+                    flops / (ms * 1e-3 + 1e-30) / 1e12);
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } log(E);
+    if (log.a) {
+        char buf[512];
+        snprintf(buf, sizeof buf, "%s,%s->%s M %lld N %lld K %lld batch %lld [%s|%s|%s] %c%c%s",
+                 sa_, sb_, sc_, M, N, K, nbatch, batch.c_str(), bcastA.c_str(), bcastB.c_str(),
+                 (sa == batch + bcastA + fa + contr) ? 'N' : (sa == batch + bcastA + contr + fa) ? 'T' : 'P',
+                 (sb == batch + bcastB + contr + fb) ? 'N' : (sb == batch + bcastB + fb + contr) ? 'T' : 'P',
+                 (sc == batch + bcastA + bcastB + fa + fb) ? "" :
+                 (sc == batch + bcastA + bcastB + fb + fa) ? " Ct" : " Cp");
+        log.text = buf;
+        log.flops = 2.0 * M * N * K * nbatch;
+        log.start();
+    }
     // operand A: [lead'][fa][contr] or [lead'][contr][fa]; lead' = batch+bcastA
     const std::string leadA = batch + bcastA;
     bool ta = false;
