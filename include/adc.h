@@ -104,6 +104,15 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
  *   "autotune"    GEMM tile choice: 0 = fixed heuristic, 1 = time the tile
  *                 configurations on the first call of each shape and keep
  *                 the fastest (default), 2 = as 1 and log the choices
+ *   "ea_layout"   EA sigma: 1 = keep the amplitudes and integrals of the
+ *                 2p1h rows also in product-ready layouts (six extra
+ *                 O^2 V^2 FP64 tensors, seven BF16 ones in the mixed mode)
+ *                 so that each large contraction is one matrix-core product,
+ *                 0 = generic contractions (permute per call), -1 = 1 when
+ *                 the extra tensors fit in half of the free device memory
+ *                 (default)
+ *   "ctr_log"     1 = time each generic contraction with HIP events and
+ *                 print its product shape on stderr (sigma then runs eagerly)
  * Errors: ADC_E_ARG for an unknown key or out-of-range value. */
 int adc_set_option(adc_ctx* ctx, const char* key, double value);
 

@@ -127,6 +127,12 @@ int adc_set_option(adc_ctx* c, const char* key, double value) {
         if (value != 0 && value != 1 && value != 2) return fail(c, ADC_E_ARG, "autotune: 0, 1 or 2");
         c->E.autotune = value != 0;
         c->E.tune_log = value == 2;
+    } else if (k == "ea_layout") {
+        // EA sigma: -1 arranged operands when they fit in memory, 0 generic
+        // contractions, 1 arranged operands
+        if (value != -1 && value != 0 && value != 1) return fail(c, ADC_E_ARG, "ea_layout: -1, 0 or 1");
+        c->ea_layout = (int)value;
+        adc::drop_graphs(c);
     } else if (k == "ctr_log") {
         // 1: time each contraction of sigma with events and print its plan on stderr
         if (value != 0 && value != 1) return fail(c, ADC_E_ARG, "ctr_log: 0 or 1");

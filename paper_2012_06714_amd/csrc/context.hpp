@@ -48,6 +48,23 @@ struct adc_ctx {
         fPi;
     adc::DBuf<adc::bf16_t> hBvv;
     bool mixed_ready = false;
+
+    // EA sigma operands rearranged so that every large contraction is one
+    // product with both summed index runs contiguous (ea_layout.hip); made on
+    // the first EA-ADC(3) sigma of each precision when they fit in memory
+    int ea_layout = -1;   // option: -1 automatic, 0 generic contraction path, 1 arranged
+    struct EaLayout {
+        // FP64: ttT1[k][d][j][c] = t~_jk^cd, ttT2[k][d][j][c] = t~_jk^dc,
+        // tT1[k][d][j][c] = t_jk^cd, tD[i][a][k][d] = t_ik^da,
+        // oovvT[i][b][j][c] = (ji|bc), tT[a][b][k][l] = t_kl^ab,
+        // G[a][j][k][l] = (jk|la) - 2 (jl|ka)
+        adc::DBuf<double> ttT1, ttT2, tT1, tD, oovvT, tT, G;
+        // mixed: BF16 copies of the product operands (rounded through FP32,
+        // as the FP32 copies are when staged) and FP32 G
+        adc::DBuf<adc::bf16_t> httT1, httT2, htT1, htD, hoovvT, htT, hovov;
+        adc::DBuf<float> fG;
+        bool ready = false, ready_mixed = false;
+    } eal;
     long long pp_slab_bytes = 4LL << 30;   // rebuilt four-index slab (particle-particle term)
 
     // sigma replayed from captured HIP graphs (sigma.hip)
@@ -106,6 +123,14 @@ void sigma(adc_ctx* c, const double* X, double* Y, int nvec, int precision);
 void sigma_eager(adc_ctx* c, const double* X, double* Y, int nvec, int precision);  // one block
 void drop_graphs(adc_ctx* c);
 void sigma_cost(const adc_ctx* c, int nvec, double* total, double* pp);
+
+// ea_layout.hip
+bool ea_layout_use(adc_ctx* c, bool mixed);     // arranged EA sigma path for this call?
+void ea_layout_build(adc_ctx* c, bool mixed);   // make the arranged operands (once each)
+// P1[z][x][j][y] = Y[z][j][x][y], P2[z][x][j][y] = Y[z][j][y][x],
+// D = P2 - 2 P1, Pm = 2 P1 - P2 (storage TB), Dw = D (storage T); null outputs skipped
+template <typename T, typename TB>
+void ea_pairs(Engine& E, const T* Y, int nvec, int O, int V, TB* P1, TB* P2, TB* D, TB* Pm, T* Dw);
 
 // spec.hip
 void spec_amplitudes(adc_ctx* c, const double* vecs, int nvec, double* Xout /*device [nvec][N]*/);

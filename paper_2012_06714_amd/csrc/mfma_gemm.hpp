@@ -71,6 +71,17 @@ void gemm_run(Engine& E, bool ta, bool tb, long long M, long long N, long long K
 // kind only names the kernel in profiles: 0 plain, 1 four-index rebuild,
 // 2 particle-particle contraction (1 and 2 are NT only)
 
+// One product C = alpha op(A) op(B) + beta C through the output index map
+// `out`, no batch.  The compute type follows the storage type TI: FP64, BF16,
+// or FP32 (multiplied in BF16 while the engine's mixed flag is set).  A plain
+// row-major output in the accumulator type goes through split-K when the
+// grid would be small.  Instantiated for (TI, TO) = (f64, f64), (f32, f32),
+// (f32, bf16), (bf16, f32), (bf16, bf16).
+template <typename TI, typename TO>
+void gemm_map(Engine& E, bool ta, bool tb, long long M, long long N, long long K, double alpha,
+              const TI* A, long long lda, const TI* B, long long ldb, double beta, TO* C,
+              GemmOut out);
+
 // Tile configuration override for tuning (-1: automatic choice per shape) and
 // the tile of a configuration id; returns -1 for an unknown id.
 void gemm_force_config(int cfg);

@@ -11,6 +11,7 @@ namespace adc {
 ADC_INST(float, bf16_t, float)
 ADC_INST(bf16_t, bf16_t, float)
 ADC_INST(bf16_t, bf16_t, bf16_t)
+ADC_INST(float, bf16_t, bf16_t)
 #undef ADC_INST
 
 template <>

@@ -9,6 +9,7 @@ namespace adc {
                                        long long, long long, AccOf<T>::type, TO*, GemmOut,       \
                                        long long, int, int, GemmInner);
 ADC_INST(float, float, float)
+ADC_INST(float, float, bf16_t)
 #undef ADC_INST
 
 template <>

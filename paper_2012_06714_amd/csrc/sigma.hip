@@ -181,6 +181,7 @@ static void sigma_adc3_ip_terms(adc_ctx* c, const Views<T>& v, const T* Y1, cons
     ctr<T>(E, T(-1), "zbkj", Y2, "kiab", v.oovv, T(1), "zaij", S2);
 }
 
+
 template <typename T>
 static Views<T> views(adc_ctx* c);
 
@@ -202,6 +203,142 @@ Views<float> views<float>(adc_ctx* c) {
 // compute type of the particle-particle GEMMs: FP64, or BF16 in the mixed mode
 template <typename T> struct PPType { using type = double; };
 template <> struct PPType<float> { using type = bf16_t; };
+
+// Operands of the arranged EA path (ea_layout.hip): TB is the storage of the
+// large product operands (FP64, or BF16 in the mixed mode).
+template <typename T>
+struct EaOps {
+    using TB = typename PPType<T>::type;
+    const TB *ttT1, *ttT2, *tT1, *tD, *oovvT, *tT, *ovov;
+    const T *G, *Bvo;
+};
+
+static EaOps<double> ea_ops(adc_ctx* c, double*) {
+    auto& L = c->eal;
+    return EaOps<double>{L.ttT1.p, L.ttT2.p, L.tT1.p, L.tD.p, L.oovvT.p, L.tT.p, c->ovov.p,
+                         L.G.p, c->Bvo.p};
+}
+static EaOps<float> ea_ops(adc_ctx* c, float*) {
+    auto& L = c->eal;
+    return EaOps<float>{L.httT1.p, L.httT2.p, L.htT1.p, L.htD.p, L.hoovvT.p, L.htT.p, L.hovov.p,
+                        L.fG.p, c->fBvo.p};
+}
+
+static GemmOut omap(long long rsplit, long long rs1, long long rs2, long long csplit, long long cs1,
+                    long long cs2) {
+    GemmOut o;
+    o.rsplit = rsplit;
+    o.rs1 = rs1;
+    o.rs2 = rs2;
+    o.csplit = csplit;
+    o.cs1 = cs1;
+    o.cs2 = cs2;
+    return o;
+}
+
+enum ArrSlot { A_P1 = 40, A_P2, A_D, A_PM, A_DW, A_W, A_X1, A_F2, A_W2, A_X, A_R, A_RP, A_WK };
+
+// EA sigma (ADC(2) terms and, for ADC(3), the second-order coupling and the
+// first-order 2p1h-2p1h terms; the particle-particle term is applied
+// separately) with every large contraction one NT product of arranged
+// operands.  The contractions are those of the generic path term by term:
+//   D[z][x][j][y] = Y_yxj - 2 Y_xyj   carries (Y_bcj - 2 Y_cbj) of the
+//                   first-order coupling and (Y_baj - 2 Y_abj) Gamma_jb,
+//   F1 = D t~  is added to D before the (jb|Q) product (both feed
+//                   sum_Q (ac|Q) W_cQ),
+//   F2 = A~ + C~  is written as [z][k][b][d] for its (bd|Q) product,
+//   S2 gets every (z,a)x(i,b) and (i,a)x(z,b) product through an output map.
+template <typename T>
+static void sigma_ea_arranged(adc_ctx* c, const T* Y1, const T* Y2, T* S1, T* S2, int nvec) {
+    using TB = typename PPType<T>::type;
+    Engine& E = c->E;
+    const bool mixed = sizeof(T) == 4;
+    ea_layout_build(c, mixed);
+    const Views<T> v = views<T>(c);
+    const long long Z = nvec, O = c->O, V = c->V, Q = c->Q;
+    const long long OV = O * V, VV = V * V, OVV = O * VV;
+    const size_t n4 = (size_t)(Z * OVV);
+    const bool o3 = c->order == 3;
+
+    // 11 block
+    ctr<T>(E, T(1), "ab", v.M11, "zb", Y1, T(0), "za", S1);
+    // pair tensors of the trial vectors
+    T* Dw = slot<T>(E, A_DW, n4);
+    TB *P1 = nullptr, *P2 = nullptr, *D = nullptr, *Pm = nullptr;
+    if (o3) {
+        P1 = slot<TB>(E, A_P1, n4);
+        P2 = slot<TB>(E, A_P2, n4);
+        D = slot<TB>(E, A_D, n4);
+        Pm = slot<TB>(E, A_PM, n4);
+    }
+    ea_pairs<T, TB>(E, Y2, nvec, (int)O, (int)V, P1, P2, D, Pm, Dw);
+    // 21: sigma_abi = -sum_Q U[a][z][Q] (ib|Q),  U = sum_c Y_c (ac|Q)
+    T* U = slot<T>(E, S_U, (size_t)(V * Z * Q));
+    ctr<T>(E, T(1), "zc", Y1, "acQ", v.Bvv, T(0), "azQ", U);
+    const GemmOut S2_zaib = omap(V, OVV, V, V, VV, 1);    // rows (z,a), columns (i,b)
+    const GemmOut S2_iazb = omap(V, VV, V, V, OVV, 1);    // rows (i,a), columns (z,b)
+    gemm_map<T, T>(E, false, true, V * Z, OV, Q, -1.0, U, Q, v.Bov, Q, 0.0, S2,
+                   omap(Z, V, OVV, V, VV, 1));
+    // 22, zeroth order
+    zeroth_order<T>(E, Y2, S2, nvec, O, (int)V, c->eo.p, c->ev.p, -1.0, 1.0);
+
+    T* W = slot<T>(E, A_W, (size_t)(Z * V * Q));
+    if (o3) {
+        const EaOps<T> a = ea_ops(c, (T*)nullptr);
+        // sigma_a += sum_jb (Y_baj - 2 Y_abj) Gamma_jb
+        gemm_map<T, T>(E, false, true, Z * V, 1, OV, 1.0, Dw, OV, v.gam, OV, 1.0, S1,
+                       GemmOut::rowmajor(1));
+        // D + F1, F1[z][b][k][d] = sum_jc D[z][b][j][c] t~_jk^cd
+        gemm_map<TB, T>(E, false, true, Z * V, OV, OV, 1.0, D, OV, a.ttT1, OV, 1.0, Dw,
+                        GemmOut::rowmajor(OV));
+        // sigma_a -= sum_jkl Y_bcj t_kl^bc [2 (jl|ka) - (jk|la)]
+        T* X1 = slot<T>(E, A_X1, (size_t)(Z * O * O * O));
+        gemm_map<T, T>(E, false, true, Z * O, O * O, VV, 1.0, Y2, VV, v.t, VV, 0.0, X1,
+                       GemmOut::rowmajor(O * O));
+        gemm_map<T, T>(E, false, true, Z, V, O * O * O, 1.0, X1, O * O * O, a.G, O * O * O, 1.0,
+                       S1, GemmOut::rowmajor(V));
+        // F2 = A~ + C~ as F2[z][k][b][d], then sigma_a += sum_kQ (sum_bd F2 (bd|Q)) (ka|Q)
+        T* F2 = slot<T>(E, A_F2, n4);
+        const GemmOut f2map = omap(V, OVV, V, V, VV, 1);
+        gemm_map<TB, T>(E, false, true, Z * V, OV, OV, 1.0, P1, OV, a.ttT1, OV, 0.0, F2, f2map);
+        gemm_map<TB, T>(E, false, true, Z * V, OV, OV, 1.0, P2, OV, a.ttT2, OV, 1.0, F2, f2map);
+        T* W2 = slot<T>(E, A_W2, (size_t)(Z * O * Q));
+        gemm_map<T, T>(E, false, false, Z * O, Q, VV, 1.0, F2, VV, v.Bvv, Q, 0.0, W2,
+                       GemmOut::rowmajor(Q));
+        gemm_map<T, T>(E, false, true, Z, V, O * Q, 1.0, W2, O * Q, a.Bvo, O * Q, 1.0, S1,
+                       GemmOut::rowmajor(V));
+        // sigma_abi -= Y_a Gamma_ib
+        gemm_map<T, T>(E, false, true, Z * V, OV, 1, -1.0, Y1, 1, v.gam, 1, 1.0, S2, S2_zaib);
+        // sigma_abi -= sum_kl (sum_c Y_c (li|kc)) t_kl^ab, the inner sum stored [z][i][k][l]
+        TB* X = slot<TB>(E, A_X, (size_t)(Z * O * O * O));
+        gemm_map<T, TB>(E, false, true, Z, O * O * O, V, 1.0, Y1, V, v.ooov, V, 0.0, X,
+                        omap(0, 0, O * O * O, O * O, 1, O));
+        gemm_map<TB, T>(E, false, true, Z * O, VV, O * O, -1.0, X, O * O, a.tT, O * O, 1.0, S2,
+                        GemmOut::rowmajor(VV));
+        // R[z][a][k][d] = (ac|kd) Y_c:  sigma_abi -= R t~_ik^bd
+        TB* R = slot<TB>(E, A_R, n4);
+        gemm_map<T, TB>(E, false, true, V * Z, OV, Q, 1.0, U, Q, v.Bov, Q, 0.0, R,
+                        omap(Z, OV, OVV, 0, 0, 1));
+        gemm_map<TB, T>(E, false, true, Z * V, OV, OV, -1.0, R, OV, a.ttT1, OV, 1.0, S2, S2_zaib);
+        // R'[z][a][k][d] = (kc|ad) Y_c:  sigma_abi += R' t_ik^bd + R'[z][b] t_ik^da
+        T* Wk = slot<T>(E, A_WK, (size_t)(Z * O * Q));
+        ctr<T>(E, T(1), "zc", Y1, "kcQ", v.Bov, T(0), "zkQ", Wk);
+        TB* Rp = slot<TB>(E, A_RP, n4);
+        gemm_map<T, TB>(E, false, true, Z * O, VV, Q, 1.0, Wk, Q, v.Bvv, Q, 0.0, Rp,
+                        omap(O, OVV, V, V, OV, 1));
+        gemm_map<TB, T>(E, false, true, Z * V, OV, OV, 1.0, Rp, OV, a.tT1, OV, 1.0, S2, S2_zaib);
+        gemm_map<TB, T>(E, false, true, OV, Z * V, OV, 1.0, a.tD, OV, Rp, OV, 1.0, S2, S2_iazb);
+        // first-order 2p1h-2p1h: (2 Y_acj - Y_caj)(jc|ib) - Y_acj (ji|bc) - Y_cbj (ji|ac)
+        gemm_map<TB, T>(E, false, true, Z * V, OV, OV, 1.0, Pm, OV, a.ovov, OV, 1.0, S2, S2_zaib);
+        gemm_map<TB, T>(E, false, true, Z * V, OV, OV, -1.0, P1, OV, a.oovvT, OV, 1.0, S2, S2_zaib);
+        gemm_map<TB, T>(E, false, true, OV, Z * V, OV, -1.0, a.oovvT, OV, P2, OV, 1.0, S2, S2_iazb);
+    }
+    // sigma_a += sum_cQ (ac|Q) W[z][c][Q],  W = sum_jb (D + F1)[z][c][j][b] (jb|Q)
+    gemm_map<T, T>(E, false, false, Z * V, Q, OV, 1.0, Dw, OV, v.Bov, Q, 0.0, W,
+                   GemmOut::rowmajor(Q));
+    gemm_map<T, T>(E, false, true, Z, V, V * Q, 1.0, W, V * Q, v.Bvv, V * Q, 1.0, S1,
+                   GemmOut::rowmajor(V));
+}
 
 template <typename T>
 void sigma_block(adc_ctx* c, const double* X, double* Yout, int nvec) {
@@ -230,11 +367,15 @@ void sigma_block(adc_ctx* c, const double* X, double* Yout, int nvec) {
     copy_rows<double, T>(E, X, dim, 0, Y1, n1, 0, nvec, n1, 0.0);
     pair_transform<double, T>(E, X, dim, n1, Y2, len2, 0, nvec, nx, np, ALI, BEI, 0.0);
 
-    sigma_adc2_terms<T>(c, v, Y1, Y2, S1, S2, nvec);
     const bool ea3 = c->order == 3 && c->kind == ADC_EA;
     const bool ip3 = c->order == 3 && c->kind == ADC_IP;
-    if (ea3) sigma_adc3_ea_terms<T>(c, v, Y1, Y2, S1, S2, nvec);
-    if (ip3) sigma_adc3_ip_terms<T>(c, v, Y1, Y2, S1, S2, nvec);
+    if (ea_layout_use(c, sizeof(T) == 4)) {
+        sigma_ea_arranged<T>(c, Y1, Y2, S1, S2, nvec);
+    } else {
+        sigma_adc2_terms<T>(c, v, Y1, Y2, S1, S2, nvec);
+        if (ea3) sigma_adc3_ea_terms<T>(c, v, Y1, Y2, S1, S2, nvec);
+        if (ip3) sigma_adc3_ip_terms<T>(c, v, Y1, Y2, S1, S2, nvec);
+    }
 
     // Z-basis result: S^{1/2} sigma_Y (+ the particle-particle term, which commutes
     // with the pair metric and acts on Z directly)

@@ -160,6 +160,8 @@ ADC_RUN_INST(float, float, float)
 ADC_RUN_INST(float, bf16_t, float)
 ADC_RUN_INST(bf16_t, bf16_t, float)
 ADC_RUN_INST(bf16_t, bf16_t, bf16_t)
+ADC_RUN_INST(float, bf16_t, bf16_t)
+ADC_RUN_INST(float, float, bf16_t)
 #undef ADC_RUN_INST
 
 // Skinny products with a long summed index (Davidson overlaps, gemv-like
@@ -195,12 +197,14 @@ static long long splitk_chunks(long long M, long long N, long long K, long long 
     return std::max<long long>(S, 1);
 }
 
+// C (accumulator type) = alpha op(A) op(B) + beta C, row-major output with
+// leading dimension ldc, through split-K when the grid would be small
 template <typename TI, typename T>
-static void gemm_any(Engine& E, bool ta, bool tb, long long M, long long N, long long K, TI alpha,
-                     const TI* A, long long lda, long long sA, const TI* B, long long ldb,
-                     long long sB, TI beta, TI* C, long long ldc, long long sC, long long batch) {
+static void gemm_any(Engine& E, bool ta, bool tb, long long M, long long N, long long K,
+                     typename AccOf<T>::type alpha, const TI* A, long long lda, long long sA,
+                     const TI* B, long long ldb, long long sB, typename AccOf<T>::type beta,
+                     typename AccOf<T>::type* C, long long ldc, long long sC, long long batch) {
     using Acc = typename AccOf<T>::type;
-    static_assert(sizeof(Acc) == sizeof(TI), "accumulator must match the output type");
     long long S = splitk_chunks(M, N, K, batch, sizeof(Acc));
     long long Kc = K;
     if (S >= 2) {
@@ -220,21 +224,72 @@ static void gemm_any(Engine& E, bool ta, bool tb, long long M, long long N, long
         in.sB = offB;
         in.sC = MNB;
         // chunks 0 .. S-2 (inner level) of every batch item (outer level)
-        gemm_run<TI, T, Acc>(E, ta, tb, M, N, Kc, (Acc)alpha, A, lda, sA, B, ldb, sB, Acc(0), part,
+        gemm_run<TI, T, Acc>(E, ta, tb, M, N, Kc, alpha, A, lda, sA, B, ldb, sB, Acc(0), part,
                              GemmOut::rowmajor(N, M * N), batch, 0, in);
-        gemm_run<TI, T, Acc>(E, ta, tb, M, N, Klast, (Acc)alpha, A + (S - 1) * offA, lda, sA,
+        gemm_run<TI, T, Acc>(E, ta, tb, M, N, Klast, alpha, A + (S - 1) * offA, lda, sA,
                              B + (S - 1) * offB, ldb, sB, Acc(0), part + (S - 1) * MNB,
                              GemmOut::rowmajor(N, M * N), batch);
         long long g = (MNB + 255) / 256;
         if (g > 4096) g = 4096;
         hipLaunchKernelGGL(k_splitk_reduce<Acc>, dim3((unsigned)g), dim3(256), 0, E.stream, part,
-                           (int)S, batch, M, N, (Acc*)C, ldc, sC, (Acc)beta);
+                           (int)S, batch, M, N, C, ldc, sC, beta);
         ADC_HIP(hipGetLastError());
         return;
     }
-    gemm_run<TI, T, TI>(E, ta, tb, M, N, K, (Acc)alpha, A, lda, sA, B, ldb, sB, (Acc)beta, C,
-                        GemmOut::rowmajor(ldc, sC), batch);
+    gemm_run<TI, T, Acc>(E, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,
+                         GemmOut::rowmajor(ldc, sC), batch);
 }
+
+// compute type of an operand storage type: FP64 -> FP64, FP32 -> BF16 in the
+// mixed mode (FP32 otherwise), BF16 -> BF16
+template <typename TI> struct CompOf { using type = TI; };
+template <> struct CompOf<float> { using type = float; };
+
+template <typename TI, typename TO>
+void gemm_map(Engine& E, bool ta, bool tb, long long M, long long N, long long K, double alpha,
+              const TI* A, long long lda, const TI* B, long long ldb, double beta, TO* C,
+              GemmOut out) {
+    if (M <= 0 || N <= 0) return;
+    E.gemm_flops += 2LL * M * N * K;
+    const bool plain = out.rsplit <= 0 && out.csplit <= 0 && out.cs2 == 1;
+    auto run = [&](auto tag) {
+        using T = decltype(tag);
+        using Acc = typename AccOf<T>::type;
+        if constexpr (std::is_same<TO, Acc>::value) {
+            if (plain) {
+                gemm_any<TI, T>(E, ta, tb, M, N, K, (Acc)alpha, A, lda, 0, B, ldb, 0, (Acc)beta, C,
+                                out.rs2, 0, 1);
+                return;
+            }
+        }
+        gemm_run<TI, T, TO>(E, ta, tb, M, N, K, (Acc)alpha, A, lda, 0, B, ldb, 0, (Acc)beta, C,
+                            out, 1);
+    };
+    if constexpr (std::is_same<TI, float>::value) {
+        if (E.bf16)
+            run(bf16_t());
+        else
+            run(float());
+    } else {
+        run(TI());
+    }
+}
+
+template void gemm_map<double, double>(Engine&, bool, bool, long long, long long, long long, double,
+                                       const double*, long long, const double*, long long, double,
+                                       double*, GemmOut);
+template void gemm_map<float, float>(Engine&, bool, bool, long long, long long, long long, double,
+                                     const float*, long long, const float*, long long, double,
+                                     float*, GemmOut);
+template void gemm_map<float, bf16_t>(Engine&, bool, bool, long long, long long, long long, double,
+                                      const float*, long long, const float*, long long, double,
+                                      bf16_t*, GemmOut);
+template void gemm_map<bf16_t, float>(Engine&, bool, bool, long long, long long, long long, double,
+                                      const bf16_t*, long long, const bf16_t*, long long, double,
+                                      float*, GemmOut);
+template void gemm_map<bf16_t, bf16_t>(Engine&, bool, bool, long long, long long, long long, double,
+                                       const bf16_t*, long long, const bf16_t*, long long, double,
+                                       bf16_t*, GemmOut);
 
 template <>
 void gemm_rm<double>(Engine& E, bool ta, bool tb, long long M, long long N, long long K, double alpha,

@@ -143,6 +143,33 @@ def test_sigma_parity_multi_tile(O, V, Q, seed, kind, order):
     assert np.abs(s_gpu - s_ref).max() <= 1e-11 * scale
 
 
+@pytest.mark.parametrize("order", ORDERS)
+@pytest.mark.parametrize("layout", [0, 1])
+def test_ea_sigma_both_contraction_paths(order, layout):
+    """The EA sigma through the generic contractions (operands permuted per
+    call) and through the arranged operands (one product per contraction,
+    results scattered by output index maps) against the oracle, in FP64 and
+    mixed precision.  O, V, Q divide no tile, k-chunk or 32-wide pair tile."""
+    from oracle.radc import RADC
+    from synthetic import random_vectors, small_system
+    O, V, Q, seed = 7, 45, 101, 9
+    eps, B = small_system(O, V, Q, seed)
+    _say(f"case ea sigma layout={layout} n={order}")
+    ref = RADC(eps, B, O, order, "ea")
+    ctx = _ctx(eps, B, O, order, "ea")
+    ctx.set_option("ea_layout", layout)
+    X = random_vectors(ref.dim, 5, seed + 500)
+    Xd = torch.tensor(X, device="cuda")
+    s64 = ctx.sigma(Xd).cpu().numpy()
+    ctx.set_option("precision", 1)
+    smx = ctx.sigma(Xd).cpu().numpy()
+    ctx.close()
+    s_ref = ref.sigma(X)
+    assert np.abs(s64 - s_ref).max() <= 1e-11 * np.abs(s_ref).max()
+    rel = np.linalg.norm(smx - s_ref, axis=1) / np.linalg.norm(s_ref, axis=1)
+    assert 1e-9 < rel.max() < 1e-2, rel
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_pp_term_blocked_rebuild(precision):
     """EA-ADC(3) with a slab too small for all a: the rebuild runs in blocks of
