@@ -96,6 +96,10 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
  *   "pp_slab_mb"  size bound in MiB of the rebuilt four-virtual slab of the
  *                 particle-particle term (default 4096); a smaller slab means
  *                 more, smaller rebuild blocks
+ *   "pp_blocks"   minimum number of blocks of a in that rebuild (default 0:
+ *                 min(12, V/8) in FP64, 1 in the mixed mode); block k
+ *                 rebuilds only the pairs b >= its first a, so more blocks
+ *                 mean fewer rebuilt flops but smaller products
  *   "workspace_limit"  bytes the context may allocate in total
  *   "graph"       1 = replay sigma from HIP graphs captured per (vector
  *                 count, precision) after an eager warm-up call (default 0)

@@ -127,6 +127,11 @@ int adc_set_option(adc_ctx* c, const char* key, double value) {
         if (value != 0 && value != 1 && value != 2) return fail(c, ADC_E_ARG, "autotune: 0, 1 or 2");
         c->E.autotune = value != 0;
         c->E.tune_log = value == 2;
+    } else if (k == "pp_blocks") {
+        if (value < 0 || value > 1e6 || value != std::floor(value))
+            return fail(c, ADC_E_ARG, "pp_blocks: a count >= 0");
+        c->pp_blocks = (int)value;
+        adc::drop_graphs(c);
     } else if (k == "ea_layout") {
         // EA sigma: -1 arranged operands when they fit in memory, 0 generic
         // contractions, 1 arranged operands

@@ -66,6 +66,7 @@ struct adc_ctx {
         bool ready = false, ready_mixed = false;
     } eal;
     long long pp_slab_bytes = 4LL << 30;   // rebuilt four-index slab (particle-particle term)
+    int pp_blocks = 0;                     // minimum number of a-blocks of that term (0: automatic)
 
     // sigma replayed from captured HIP graphs (sigma.hip)
     struct SigmaGraph {

@@ -73,14 +73,23 @@ void gemm_run(Engine& E, bool ta, bool tb, long long M, long long N, long long K
 
 // One product C = alpha op(A) op(B) + beta C through the output index map
 // `out`, no batch.  The compute type follows the storage type TI: FP64, BF16,
-// or FP32 (multiplied in BF16 while the engine's mixed flag is set).  A plain
-// row-major output in the accumulator type goes through split-K when the
-// grid would be small.  Instantiated for (TI, TO) = (f64, f64), (f32, f32),
+// or FP32 (multiplied in BF16 while the engine's mixed flag is set).  An
+// output in the accumulator type goes through split-K when the grid would be
+// small (partial products reduced in a fixed order, then stored through the
+// map).  Instantiated for (TI, TO) = (f64, f64), (f32, f32),
 // (f32, bf16), (bf16, f32), (bf16, bf16).
 template <typename TI, typename TO>
 void gemm_map(Engine& E, bool ta, bool tb, long long M, long long N, long long K, double alpha,
               const TI* A, long long lda, const TI* B, long long ldb, double beta, TO* C,
               GemmOut out);
+
+// The same for compute type T with the output in its accumulator type,
+// tagged with a profile kind (split-K keeps the tag).  Instantiated for
+// (TI, T) = (f64, f64), (bf16, bf16).
+template <typename TI, typename T>
+void gemm_acc(Engine& E, bool ta, bool tb, long long M, long long N, long long K,
+              typename AccOf<T>::type alpha, const TI* A, long long lda, const TI* B, long long ldb,
+              typename AccOf<T>::type beta, typename AccOf<T>::type* C, GemmOut out, int kind);
 
 // Tile configuration override for tuning (-1: automatic choice per shape) and
 // the tile of a configuration id; returns -1 for an unknown id.

@@ -137,8 +137,10 @@ k_gemm(const TI* __restrict__ A, const TI* __restrict__ B, TO* __restrict__ C, G
     constexpr int NSTEP = BK / MT::KSTEP;
     static_assert(TM >= 1 && TN >= 1, "tile too small");
 
-    __shared__ __attribute__((aligned(16))) T sA[2][BM * LDK];
-    __shared__ __attribute__((aligned(16))) T sB[2][BN * LDK];
+    // operand tiles, double-buffered; reused by the epilogue to stage results
+    __shared__ __attribute__((aligned(16))) T smem[2 * (BM + BN) * LDK];
+    auto sA = [&](int b) -> T* { return smem + b * (BM * LDK); };
+    auto sB = [&](int b) -> T* { return smem + 2 * BM * LDK + b * (BN * LDK); };
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -270,11 +272,11 @@ k_gemm(const TI* __restrict__ A, const TI* __restrict__ B, TO* __restrict__ C, G
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
                     fa[i] = *reinterpret_cast<const double*>(
-                        sA[cur] + (wm * WM + i * 16 + li) * LDK + lg * (BK / 4) + s);
+                        sA(cur) + (wm * WM + i * 16 + li) * LDK + lg * (BK / 4) + s);
 #pragma unroll
                 for (int j = 0; j < TN; ++j)
                     fb[j] = *reinterpret_cast<const double*>(
-                        sB[cur] + (wn * WN + j * 16 + li) * LDK + lg * (BK / 4) + s);
+                        sB(cur) + (wn * WN + j * 16 + li) * LDK + lg * (BK / 4) + s);
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -293,11 +295,11 @@ k_gemm(const TI* __restrict__ A, const TI* __restrict__ B, TO* __restrict__ C, G
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
                     fa[i] = *reinterpret_cast<const uint4*>(
-                        sA[cur] + (wm * WM + i * 16 + li) * LDK + lg * (BK / 4) + s * 8);
+                        sA(cur) + (wm * WM + i * 16 + li) * LDK + lg * (BK / 4) + s * 8);
 #pragma unroll
                 for (int j = 0; j < TN; ++j)
                     fb[j] = *reinterpret_cast<const uint4*>(
-                        sB[cur] + (wn * WN + j * 16 + li) * LDK + lg * (BK / 4) + s * 8);
+                        sB(cur) + (wn * WN + j * 16 + li) * LDK + lg * (BK / 4) + s * 8);
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -311,13 +313,13 @@ k_gemm(const TI* __restrict__ A, const TI* __restrict__ B, TO* __restrict__ C, G
             uint4 fa[TM][2], fb[TN][2];
 #pragma unroll
             for (int i = 0; i < TM; ++i) {
-                const T* p = sA[cur] + (wm * WM + i * 16 + li) * LDK + lg * (BK / 4);
+                const T* p = sA(cur) + (wm * WM + i * 16 + li) * LDK + lg * (BK / 4);
                 fa[i][0] = reinterpret_cast<const uint4*>(p)[0];
                 fa[i][1] = reinterpret_cast<const uint4*>(p)[1];
             }
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
-                const T* p = sB[cur] + (wn * WN + j * 16 + li) * LDK + lg * (BK / 4);
+                const T* p = sB(cur) + (wn * WN + j * 16 + li) * LDK + lg * (BK / 4);
                 fb[j][0] = reinterpret_cast<const uint4*>(p)[0];
                 fb[j][1] = reinterpret_cast<const uint4*>(p)[1];
             }
@@ -342,8 +344,8 @@ k_gemm(const TI* __restrict__ A, const TI* __restrict__ B, TO* __restrict__ C, G
             load_safe(A, g.lda, TrA{}, m0, g.M, BM, ra, CA, 0);
             load_safe(B, g.ldb, TrB{}, n0, g.N, BN, rb, CB, 0);
         }
-        store(sA[0], TrA{}, BM, ra, CA);
-        store(sB[0], TrB{}, BN, rb, CB);
+        store(sA(0), TrA{}, BM, ra, CA);
+        store(sB(0), TrB{}, BN, rb, CB);
         __syncthreads();
         long long kt = 0;
         // the next tile is a fast one
@@ -352,8 +354,8 @@ k_gemm(const TI* __restrict__ A, const TI* __restrict__ B, TO* __restrict__ C, G
             load_fast(A, g.lda, TrA{}, m0, g.M, BM, ra, CA, (kt + 1) * BK);
             load_fast(B, g.ldb, TrB{}, n0, g.N, BN, rb, CB, (kt + 1) * BK);
             compute(cur);
-            store(sA[cur ^ 1], TrA{}, BM, ra, CA);
-            store(sB[cur ^ 1], TrB{}, BN, rb, CB);
+            store(sA(cur ^ 1), TrA{}, BM, ra, CA);
+            store(sB(cur ^ 1), TrB{}, BN, rb, CB);
             __syncthreads();
         }
         // the next tile needs bounds checks
@@ -362,31 +364,75 @@ k_gemm(const TI* __restrict__ A, const TI* __restrict__ B, TO* __restrict__ C, G
             load_safe(A, g.lda, TrA{}, m0, g.M, BM, ra, CA, (kt + 1) * BK);
             load_safe(B, g.ldb, TrB{}, n0, g.N, BN, rb, CB, (kt + 1) * BK);
             compute(cur);
-            store(sA[cur ^ 1], TrA{}, BM, ra, CA);
-            store(sB[cur ^ 1], TrB{}, BN, rb, CB);
+            store(sA(cur ^ 1), TrA{}, BM, ra, CA);
+            store(sB(cur ^ 1), TrB{}, BN, rb, CB);
             __syncthreads();
         }
         compute(kt & 1);
     }
 
     // ---- epilogue -------------------------------------------------------
+    // Each wave stages its sub-tile (alpha applied) in LDS, in passes over
+    // column slices when the whole tile does not fit, and stores it back in
+    // runs of 4 consecutive columns: one vector store per run when the run is
+    // contiguous and aligned in the output map, element stores otherwise.
+    constexpr int NW = WGM * WGN;
+    constexpr int SMEM_BYTES = 2 * (BM + BN) * LDK * (int)sizeof(T);
+    constexpr int PAD = 16 / (int)sizeof(acc_t);
+    constexpr int NPASS = (NW * WM * (WN + PAD) * (int)sizeof(acc_t) <= SMEM_BYTES)         ? 1
+                          : (NW * WM * (WN / 2 + PAD) * (int)sizeof(acc_t) <= SMEM_BYTES) ? 2
+                                                                                            : 4;
+    constexpr int WNP = WN / NPASS;          // columns per pass
+    constexpr int TNP = TN / NPASS;          // 16-column blocks per pass
+    constexpr int LDC = WNP + PAD;           // staged row (elements)
+    constexpr int RUNS = WM * WNP / 4;       // runs of 4 per wave and pass
+    static_assert(TN % NPASS == 0 && RUNS % 64 == 0, "epilogue tiling");
+    static_assert(NW * WM * LDC * (int)sizeof(acc_t) <= SMEM_BYTES, "epilogue staging");
+    typedef TO to4 __attribute__((ext_vector_type(4)));
+    acc_t* stage = reinterpret_cast<acc_t*>(smem) + wave * (WM * LDC);
 #pragma unroll
-    for (int i = 0; i < TM; ++i) {
+    for (int p = 0; p < NPASS; ++p) {
+        __syncthreads();    // operand tiles (or the previous pass) no longer read
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const long long m = m0 + wm * WM + i * 16 + MT::row(lg, r);
-            if (m >= g.M) continue;
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int jj = 0; jj < TNP; ++jj)
+                    stage[(i * 16 + MT::row(lg, r)) * LDC + jj * 16 + li] =
+                        alpha * acc[i][p * TNP + jj][r];
+        __syncthreads();
+#pragma unroll 4
+        for (int q = lane; q < RUNS; q += 64) {
+            const int row = q / (WNP / 4), c4 = (q % (WNP / 4)) * 4;
+            const long long m = m0 + wm * WM + row;
+            const long long n = n0 + wn * WN + p * WNP + c4;
+            if (m >= g.M || n >= g.N) continue;
+            const acc_t* sv = stage + row * LDC + c4;
             const long long m1 = m / g.rsplit, m2 = m - m1 * g.rsplit;
-            const long long rowoff = m1 * g.rs1 + m2 * g.rs2;
+            const long long n1 = n / g.csplit, n2 = n - n1 * g.csplit;
+            TO* dst = C + m1 * g.rs1 + m2 * g.rs2 + n1 * g.cs1 + n2 * g.cs2;
+            const bool run = n + 3 < g.N && g.cs2 == 1 && n2 + 3 < g.csplit &&
+                             (reinterpret_cast<uintptr_t>(dst) % (4 * sizeof(TO))) == 0;
+            if (run) {
+                to4 o;
+                if (beta != acc_t(0)) {
+                    const to4 old = *reinterpret_cast<const to4*>(dst);
 #pragma unroll
-            for (int j = 0; j < TN; ++j) {
-                const long long n = n0 + wn * WN + j * 16 + li;
-                if (n >= g.N) continue;
-                const long long n1 = n / g.csplit, n2 = n - n1 * g.csplit;
-                TO* dst = C + rowoff + n1 * g.cs1 + n2 * g.cs2;
-                acc_t v = alpha * acc[i][j][r];
-                if (beta != acc_t(0)) v += beta * (acc_t)(*dst);
-                *dst = to_out<TO, acc_t>(v);
+                    for (int e = 0; e < 4; ++e) o[e] = to_out<TO, acc_t>(sv[e] + beta * (acc_t)old[e]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) o[e] = to_out<TO, acc_t>(sv[e]);
+                }
+                *reinterpret_cast<to4*>(dst) = o;
+            } else {
+                for (int e = 0; e < 4 && n + e < g.N; ++e) {
+                    const long long ne = n + e, ne1 = ne / g.csplit, ne2 = ne - ne1 * g.csplit;
+                    TO* de = C + m1 * g.rs1 + m2 * g.rs2 + ne1 * g.cs1 + ne2 * g.cs2;
+                    acc_t v = sv[e];
+                    if (beta != acc_t(0)) v += beta * (acc_t)(*de);
+                    *de = to_out<TO, acc_t>(v);
+                }
             }
         }
     }
@@ -427,21 +473,27 @@ static void launch_tiles(hipStream_t st, bool ta, bool tb, const TI* A, const TI
 
 // Tile configurations: (BM, BN, waves in M, waves in N).
 //   0: 64x64 (4x1)    1: 128x128 (2x2)   2: 128x128 (4x2)   3: 128x64 (2x2)
-//   4: 256x128 (2x2)  5: 256x256 (2x2)   6: 256x128 (4x2)
+//   4: 256x128 (2x2)  5: 256x256 (2x2)   6: 256x128 (4x2)   7: 256x256 (4x2)
+// The 8-wave 256x256 tile gives each wave a 64x128 block: half the LDS reads
+// per multiply of the 64x64 blocks, which is what limits BF16.
 
 // configurations compiled for each compute type (the rest fall back to 0)
 template <typename T> static bool cfg_available(int cfg);
 template <> inline bool cfg_available<double>(int cfg) { return cfg == 0 || cfg == 2 || cfg == 3; }
 template <> inline bool cfg_available<float>(int cfg) { return cfg == 0 || cfg == 1 || cfg == 2; }
-template <> inline bool cfg_available<bf16_t>(int cfg) { return cfg == 0 || cfg == 1 || cfg == 6; }
+template <> inline bool cfg_available<bf16_t>(int cfg) {
+    return cfg == 0 || cfg == 1 || cfg == 6 || cfg == 7;
+}
 
 // untuned choice: the large tile when both sides fill it and the grid gives
-// the chip at least two rounds of workgroups, else 64x64
+// the chip at least one (256x256) or two (128x128) rounds of workgroups, else
+// 64x64
 template <typename T>
 static int choose_cfg(long long M, long long N, long long batch) {
     auto wgs = [&](int bm, int bn) { return ((M + bm - 1) / bm) * ((N + bn - 1) / bn) * batch; };
     const bool big = M >= 256 && N >= 256 && wgs(128, 128) >= 512;
     if (sizeof(T) == 8) return big ? 2 : 0;
+    if (sizeof(T) == 2 && M >= 512 && N >= 512 && wgs(256, 256) >= 256) return 7;
     return big ? 1 : 0;
 }
 
@@ -520,6 +572,7 @@ void mfma_gemm(hipStream_t st, bool ta, bool tb, long long M, long long N, long 
         switch (cfg) {
             ADC_CFG(1, 128, 128, 2, 2)
             ADC_CFG(6, 256, 128, 4, 2)
+            ADC_CFG(7, 256, 256, 4, 2)
             default: ADC_CFG(0, 64, 64, 4, 1)
         }
     }

@@ -170,17 +170,19 @@ ADC_RUN_INST(float, float, bf16_t)
 // into partial results [chunk][batch][M][N], then reduce them in a fixed order.
 template <typename A>
 __global__ void k_splitk_reduce(const A* __restrict__ part, int S, long long batch, long long M,
-                                long long N, A* __restrict__ C, long long ldc, long long sC,
-                                A beta) {
+                                long long N, A* __restrict__ C, GemmOut o, A beta) {
     const long long MN = M * N, tot = batch * MN;
+    const long long rsplit = o.rsplit > 0 ? o.rsplit : M, csplit = o.csplit > 0 ? o.csplit : N;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
          e += (long long)gridDim.x * blockDim.x) {
         A v = 0;
         for (int s = 0; s < S; ++s) v += part[s * tot + e];
         const long long b = e / MN, r = e - b * MN;
         const long long m = r / N, n = r - m * N;
-        A* o = C + b * sC + m * ldc + n;
-        *o = (beta == A(0)) ? v : beta * *o + v;
+        const long long m1 = m / rsplit, n1 = n / csplit;
+        A* dst = C + b * o.sC + m1 * o.rs1 + (m - m1 * rsplit) * o.rs2 + n1 * o.cs1 +
+                 (n - n1 * csplit) * o.cs2;
+        *dst = (beta == A(0)) ? v : beta * *dst + v;
     }
 }
 
@@ -203,7 +205,7 @@ template <typename TI, typename T>
 static void gemm_any(Engine& E, bool ta, bool tb, long long M, long long N, long long K,
                      typename AccOf<T>::type alpha, const TI* A, long long lda, long long sA,
                      const TI* B, long long ldb, long long sB, typename AccOf<T>::type beta,
-                     typename AccOf<T>::type* C, long long ldc, long long sC, long long batch) {
+                     typename AccOf<T>::type* C, GemmOut out, long long batch, int kind) {
     using Acc = typename AccOf<T>::type;
     long long S = splitk_chunks(M, N, K, batch, sizeof(Acc));
     long long Kc = K;
@@ -212,7 +214,7 @@ static void gemm_any(Engine& E, bool ta, bool tb, long long M, long long N, long
         Kc = (Kc + 63) / 64 * 64;
         S = (K + Kc - 1) / Kc;
     }
-    if (S >= 2) {
+    if (S >= 2 && (kind == 0 || (!ta && tb))) {
         const long long Klast = K - (S - 1) * Kc;
         const long long MNB = M * N * batch;
         Acc* part = (Acc*)E.scratch.get(31, sizeof(Acc) * S * MNB);
@@ -225,20 +227,33 @@ static void gemm_any(Engine& E, bool ta, bool tb, long long M, long long N, long
         in.sC = MNB;
         // chunks 0 .. S-2 (inner level) of every batch item (outer level)
         gemm_run<TI, T, Acc>(E, ta, tb, M, N, Kc, alpha, A, lda, sA, B, ldb, sB, Acc(0), part,
-                             GemmOut::rowmajor(N, M * N), batch, 0, in);
+                             GemmOut::rowmajor(N, M * N), batch, kind, in);
         gemm_run<TI, T, Acc>(E, ta, tb, M, N, Klast, alpha, A + (S - 1) * offA, lda, sA,
                              B + (S - 1) * offB, ldb, sB, Acc(0), part + (S - 1) * MNB,
-                             GemmOut::rowmajor(N, M * N), batch);
+                             GemmOut::rowmajor(N, M * N), batch, kind);
         long long g = (MNB + 255) / 256;
         if (g > 4096) g = 4096;
         hipLaunchKernelGGL(k_splitk_reduce<Acc>, dim3((unsigned)g), dim3(256), 0, E.stream, part,
-                           (int)S, batch, M, N, C, ldc, sC, beta);
+                           (int)S, batch, M, N, C, out, beta);
         ADC_HIP(hipGetLastError());
         return;
     }
-    gemm_run<TI, T, Acc>(E, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,
-                         GemmOut::rowmajor(ldc, sC), batch);
+    gemm_run<TI, T, Acc>(E, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, out, batch,
+                         kind);
 }
+
+template <typename TI, typename T>
+void gemm_acc(Engine& E, bool ta, bool tb, long long M, long long N, long long K,
+              typename AccOf<T>::type alpha, const TI* A, long long lda, const TI* B, long long ldb,
+              typename AccOf<T>::type beta, typename AccOf<T>::type* C, GemmOut out, int kind) {
+    gemm_any<TI, T>(E, ta, tb, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, out, 1, kind);
+}
+template void gemm_acc<double, double>(Engine&, bool, bool, long long, long long, long long, double,
+                                       const double*, long long, const double*, long long, double,
+                                       double*, GemmOut, int);
+template void gemm_acc<bf16_t, bf16_t>(Engine&, bool, bool, long long, long long, long long, float,
+                                       const bf16_t*, long long, const bf16_t*, long long, float,
+                                       float*, GemmOut, int);
 
 // compute type of an operand storage type: FP64 -> FP64, FP32 -> BF16 in the
 // mixed mode (FP32 otherwise), BF16 -> BF16
@@ -251,16 +266,13 @@ void gemm_map(Engine& E, bool ta, bool tb, long long M, long long N, long long K
               GemmOut out) {
     if (M <= 0 || N <= 0) return;
     E.gemm_flops += 2LL * M * N * K;
-    const bool plain = out.rsplit <= 0 && out.csplit <= 0 && out.cs2 == 1;
     auto run = [&](auto tag) {
         using T = decltype(tag);
         using Acc = typename AccOf<T>::type;
         if constexpr (std::is_same<TO, Acc>::value) {
-            if (plain) {
-                gemm_any<TI, T>(E, ta, tb, M, N, K, (Acc)alpha, A, lda, 0, B, ldb, 0, (Acc)beta, C,
-                                out.rs2, 0, 1);
-                return;
-            }
+            gemm_any<TI, T>(E, ta, tb, M, N, K, (Acc)alpha, A, lda, 0, B, ldb, 0, (Acc)beta, C, out,
+                            1, 0);
+            return;
         }
         gemm_run<TI, T, TO>(E, ta, tb, M, N, K, (Acc)alpha, A, lda, 0, B, ldb, 0, (Acc)beta, C,
                             out, 1);
@@ -298,8 +310,8 @@ void gemm_rm<double>(Engine& E, bool ta, bool tb, long long M, long long N, long
                      long long batch) {
     if (M == 0 || N == 0 || batch == 0) return;
     E.gemm_flops += 2LL * M * N * K * batch;
-    gemm_any<double, double>(E, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC,
-                             batch);
+    gemm_any<double, double>(E, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,
+                             GemmOut::rowmajor(ldc, sC), batch, 0);
 }
 
 template <>
@@ -310,11 +322,11 @@ void gemm_rm<float>(Engine& E, bool ta, bool tb, long long M, long long N, long 
     if (M == 0 || N == 0 || batch == 0) return;
     E.gemm_flops += 2LL * M * N * K * batch;
     if (E.bf16)
-        gemm_any<float, bf16_t>(E, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc,
-                                sC, batch);
+        gemm_any<float, bf16_t>(E, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,
+                                GemmOut::rowmajor(ldc, sC), batch, 0);
     else
-        gemm_any<float, float>(E, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC,
-                               batch);
+        gemm_any<float, float>(E, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,
+                               GemmOut::rowmajor(ldc, sC), batch, 0);
 }
 
 // ---------------------------------------------------------------------------

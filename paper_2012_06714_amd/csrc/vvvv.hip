@@ -10,10 +10,12 @@
 // whose epilogue scatters the result into the slab K[a][b][c][d].  The slab
 // then serves two contractions, both GEMMs contiguous in the summed pair:
 //   out[x][a][b] = sum_(cd) in[x][(c,d)]  K[a][b][(c,d)]          (b >= a0)
-//   out[x][b][a] = sum_(cd) inT[x][(c,d)] K[a][b][(c,d)]          (b >= a0 + na)
+//   out[x][b][a] = sum_(cd) inT[x][(c,d)] K[a][b][(c,d)]          (b >= a0)
 // where inT[x][c][d] = in[x][d][c]; pairs with b < a0 were produced as mirrors
-// by earlier blocks.  The rebuild costs Naux V^3 (V + na) flops instead of
-// 2 Naux V^4, the contraction 2 nx V^4 as before.
+// by earlier blocks, and pairs with both a and b in the block are written by
+// both products (the same value).  The rebuild of a block costs 2 Naux na V^2 (V - a0)
+// flops, Naux V^3 (V + na) over all blocks of size na instead of 2 Naux V^4;
+// the contraction 2 nx V^4 as before.
 #include "context.hpp"
 
 #include <algorithm>
@@ -27,7 +29,15 @@ void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx) {
     if (nx <= 0) return;
     long long ta_max = std::max<long long>(1, c->pp_slab_bytes / (long long)(sizeof(T) * V3));
     ta_max = std::min(ta_max, V);
-    const long long nblk = (V + ta_max - 1) / ta_max;
+    // more blocks rebuild fewer mirrored pairs (Naux V^3 (V + na) flops) but
+    // make smaller products: at least pp_blocks of them (default: FP64, whose
+    // products run near the matrix-core peak at any size, 12 blocks of at
+    // least 8 values of a; BF16, whose short-K rebuild is bound by its
+    // stores, as few as the slab allows)
+    const long long want = c->pp_blocks > 0 ? c->pp_blocks
+                           : sizeof(T) == 8 ? std::min<long long>(12, V / 8)
+                                            : 1;
+    const long long nblk = std::min(V, std::max((V + ta_max - 1) / ta_max, want));
     const long long ta = (V + nblk - 1) / nblk;            // balanced a-blocks
     T* K = (T*)E.scratch.get(30, sizeof(T) * ta * V3);
     T* inT = nblk > 1 ? (T*)E.scratch.get(29, sizeof(T) * nx * VV) : nullptr;
@@ -50,19 +60,22 @@ void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx) {
         direct.csplit = nb;
         direct.cs1 = V;
         direct.cs2 = 1;
-        gemm_run<T, T, TO>(E, false, true, nx, na * nb, VV, A(1), in, VV, 0, K, VV, 0, A(0),
-                            out + a0 * V + a0, direct, 1, 2);
+        gemm_acc<T, T>(E, false, true, nx, na * nb, VV, A(1), in, VV, K, VV, A(0),
+                       out + a0 * V + a0, direct, 2);
         E.gemm_flops += 2LL * na * V * nb * V * Q + 2LL * nx * na * nb * VV;
         if (nb > na) {
-            // mirrors: one GEMM per a, columns b = a0+na .. V-1 -> out[x][b][a]
-            GemmOut mirror;
+            // mirrors out[x][b][a] = sum_(cd) inT[x][(c,d)] K[a][b][(c,d)] as one product
+            // over all columns (a, b >= a0): the pairs with b inside the block repeat
+            // direct results of the same value, which costs na/nb of the product but
+            // keeps every operand row contiguous
+            GemmOut mirror;                                // x x (a, b-a0) -> out[x][b][a]
             mirror.rs2 = VV;
+            mirror.csplit = nb;
+            mirror.cs1 = 1;
             mirror.cs2 = V;
-            mirror.sC = 1;
-            gemm_run<T, T, TO>(E, false, true, nx, nb - na, VV, A(1), inT, VV, 0,
-                                K + na * VV, VV, nb * VV, A(0), out + (a0 + na) * V + a0, mirror,
-                                na, 2);
-            E.gemm_flops += 2LL * nx * na * (nb - na) * VV;
+            gemm_acc<T, T>(E, false, true, nx, na * nb, VV, A(1), inT, VV, K, VV, A(0),
+                           out + a0 * V + a0, mirror, 2);
+            E.gemm_flops += 2LL * nx * na * nb * VV;
         }
     }
 }
