@@ -27,7 +27,7 @@ PEAKS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 # counter runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, the factors of a plain
 # 1 GiB copy), summarised in profiles/pp_term_ea_adc3_o20v180_hbm_bytes.md.
 # Valid for the kernels as measured; re-measure whenever they change.
-PP_TRAFFIC = {("ea-adc3-o20v180", "fp64"): 5.108e10, ("ea-adc3-o20v180", "mixed"): 1.231e10}
+PP_TRAFFIC = {("ea-adc3-o20v180", "fp64"): 4.9786e+10, ("ea-adc3-o20v180", "mixed"): 7.3463e+09}
 HBM_GBPS = 8000.0
 
 
