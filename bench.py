@@ -12,6 +12,9 @@ bounded sample of the same workload (rank 0 only).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
                        [--precision fp64|mixed] [--no-davidson] [--no-cpu]
+       python bench.py --workload c5 [--systems 64] [--max-nocc N]
+         (the batched EA-ADC(2) family: lockstep solves with one graph launch
+          per iteration against one-by-one solves)
 """
 import argparse
 import json
@@ -53,6 +56,105 @@ def cpu_baseline(workload_key, nvec_sample=1):
     return dt, t_setup, cores, ref
 
 
+def bench_batch(args):
+    """Batched EA-ADC(2) workload: `systems` uneven systems of the seeded family
+    (O ~ U{10..40}, V ~ U{8O..12O}, Naux = 3V), in groups of `group` systems
+    resident together.  Each group is solved in lockstep (sigma of every
+    active system replayed from its own captured graph, issued over four
+    streams), then concurrently (eight host threads, each running the
+    single-system solver on the next system on a stream of its own), then
+    one after another with the single-system solver (graphs on as well).
+    value = systems solved per second by the faster of the two batched modes
+    (setup excluded)."""
+    import numpy as np
+    import torch
+    import paper_2012_06714_amd as adc
+    from synthetic import make_batch_system
+    dev = torch.device("cuda:0")
+    nroots, block, max_space = 4, 8, 64
+    t_setup = t_batch = t_seq = t_conc = 0.0
+    fl_batch = 0.0
+    lock_its, sys_its, launches, captures, converged = 0, [], 0, 0, 0
+    dev_e = 0.0
+    dims = []
+    for g0 in range(0, args.systems, args.group):
+        ctxs = []
+        t0 = time.perf_counter()
+        for s in range(g0, min(args.systems, g0 + args.group)):
+            eps, B, (O, V, Q) = make_batch_system(s, args.max_nocc)
+            Bd = torch.tensor(B, device=dev)
+            del B
+            c = adc.Context(torch.tensor(eps, device=dev), Bd, O, 2, "ea")
+            del Bd
+            for k, v in (("tol_e", 1e-8), ("tol_r", 1e-5), ("block", block),
+                         ("max_space", max_space), ("max_iter", 400), ("graph", 1)):
+                c.set_option(k, v)
+            ctxs.append(c)
+            dims.append(c.dim)
+            log(f"bench: system {s}: O={O} V={V} Naux={Q} dim {c.dim}")
+        torch.cuda.synchronize()
+        t_setup += time.perf_counter() - t0
+        flops1 = [c.sigma_flops(1)[0] for c in ctxs]
+        t0 = time.perf_counter()
+        e, P, it, st, stats = adc.batch_davidson(ctxs, nroots, use_graph=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        t_batch += dt
+        fl_batch += sum(f * c.stats()["sigma_vectors"] for f, c in zip(flops1, ctxs))
+        lock_its += stats["iterations"]
+        launches += stats["graph_launches"]
+        captures += stats["captures"]
+        converged += int(np.sum(st == 0))
+        sys_its += [int(x) for x in it]
+        log(f"bench: systems {g0}..{g0 + len(ctxs) - 1}: lockstep solve {dt:.2f} s, "
+            f"{stats['iterations']} iterations, per system {int(np.min(it))}..{int(np.max(it))}")
+        t0 = time.perf_counter()
+        ec, _, _, stc, _ = adc.batch_davidson(ctxs, nroots, use_graph=True, concurrent=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        t_conc += dt
+        dev_e = max(dev_e, float(np.max(np.abs(ec - e))))
+        log(f"bench: systems {g0}..{g0 + len(ctxs) - 1}: concurrent solve {dt:.2f} s")
+        t0 = time.perf_counter()
+        e_seq = []
+        for c in ctxs:
+            es, _, _, _, _ = c.davidson(nroots, want_vectors=False)
+            e_seq.append(es)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        t_seq += dt
+        dev_e = max(dev_e, float(np.max(np.abs(np.array(e_seq) - e))))
+        log(f"bench: systems {g0}..{g0 + len(ctxs) - 1}: one by one {dt:.2f} s")
+        for c in ctxs:
+            c.close()
+        del ctxs
+        torch.cuda.empty_cache()
+    n = args.systems
+    log(f"bench: {n} systems: lockstep {t_batch:.2f} s, concurrent {t_conc:.2f} s, one by one {t_seq:.2f} s, "
+        f"max |E(lockstep) - E(single)| {dev_e:.2e} Eh, setup {t_setup:.1f} s")
+    out = {
+        "metric": "EA-ADC(2) batched Davidson: systems solved per second",
+        "value": n / min(t_batch, t_conc), "unit": "systems/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": min(t_batch, t_conc) * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batched ea-adc2, {n} systems (seeds 0..{n - 1}), groups of {args.group}",
+                   "nroots": nroots, "block": block, "max_space": max_space,
+                   "max_nocc": args.max_nocc, "dims": [min(dims), max(dims), sum(dims)],
+                   "setup_s": t_setup},
+        "lockstep": {"seconds": t_batch, "iterations": lock_its, "graph_replays": launches,
+                     "captures": captures, "sigma_tflops": fl_batch / t_batch / 1e12,
+                     "converged": converged, "system_iterations": [min(sys_its), max(sys_its),
+                                                                    float(np.mean(sys_its))]},
+        "concurrent": {"seconds": t_conc, "threads": 8},
+        "one_by_one": {"seconds": t_seq, "lockstep_speedup": t_seq / t_batch,
+                       "concurrent_speedup": t_seq / t_conc,
+                       "max_energy_difference_Eh": dev_e},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,12 +168,20 @@ def main():
     ap.add_argument("--verbose", action="store_true", help="per-iteration solver lines on stderr")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a plain 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--systems", type=int, default=64, help="batched workload: number of systems")
+    ap.add_argument("--group", type=int, default=16,
+                    help="batched workload: systems resident and solved together")
+    ap.add_argument("--max-nocc", type=int, default=None,
+                    help="batched workload: cap on the occupied count (smaller stand-ins)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding of the sigma product is a design note, not built.",
               file=sys.stderr)
         return 2
+
+    if args.workload in ("c5", "batch"):
+        return bench_batch(args)
 
     import numpy as np
     import torch

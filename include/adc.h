@@ -92,7 +92,8 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
  *   "tol_e"       eigenvalue change tolerance in Eh (default 1e-8)
  *   "tol_r"       residual norm tolerance, in units of max(1, |theta|) for
  *                 each root (default sqrt(tol_e))
- *   "verbose"     0/1: per-iteration line on stderr
+ *   "verbose"     1: per-iteration line on stderr; 2: also the solver's
+ *                 wall time per phase (synchronising after each phase)
  *   "pp_slab_mb"  size bound in MiB of the rebuilt four-virtual slab of the
  *                 particle-particle term (default 4096); a smaller slab means
  *                 more, smaller rebuild blocks
@@ -139,7 +140,8 @@ int adc_sigma(adc_ctx* ctx, const double* X, double* Y, int nvec);
  * (steps 4-5): initial guesses are unit vectors at the smallest diagonal
  * entries unless adc_set_guess provided vectors; the diagonal
  * preconditioner (theta - D)^-1 corrects the residuals.  Converged when
- * every root changes by <= tol_e and has residual norm
+ * every root changes by <= max(tol_e, 8 eps |theta|) (eps = 2^-52: changes
+ * below the FP64 resolution of theta are rounding) and has residual norm
  * <= tol_r max(1, |theta|).
  * energies, spec_factors: host [nroots] (written; spec_factors may be NULL);
  * P = 2 sum_p |X_p|^2 (Eq. 50, the sum over both spin components).
@@ -195,19 +197,26 @@ int adc_last_stats(const adc_ctx* ctx, int* iters, long long* sigma_vectors,
 
 /* Several systems solved together (not in the paper: batching of its step 4
  * over independent systems).  ctxs: nsys distinct contexts, each set up and
- * configured as for adc_davidson; their solvers advance in lockstep and each
- * iteration applies sigma to the new trial vectors of every active system in
- * one HIP graph launch (use_graph != 0; the graph has one branch per system
- * on a few default-priority streams and is re-captured when the set of
- * active systems or their vector counts change), or system by system
- * (use_graph = 0).  Results equal those of adc_davidson on each context.
+ * configured as for adc_davidson.  flags:
+ *   bit 0 (1): sigma replayed from each system's own captured graphs (one per
+ *              vector count and precision, reused across iterations);
+ *   bit 1 (2): concurrent instead of lockstep: up to 8 host threads each run
+ *              the single-system solver on the next unsolved system, on a
+ *              stream of its own when the context uses the null stream, so
+ *              that the host work of one solve overlaps the device work of
+ *              the others.
+ * Without bit 1 the solvers advance in lockstep and each iteration applies
+ * sigma to the new trial vectors of every active system, issued back to back
+ * over a few default-priority streams.  Results equal those of adc_davidson
+ * on each context.
  * energies, spec_factors: host [nsys][nroots] (spec_factors may be NULL);
  * n_iter, status: host [nsys] (may be NULL; status per system as
- * adc_davidson returns it); stats: host [3] or NULL: lockstep iterations,
- * graph launches, graph captures.  Returns ADC_OK when every system
- * converged, else the first non-OK status; the message of a failure is
- * adc_last_error(NULL). */
-int adc_batch_davidson(adc_ctx* const* ctxs, int nsys, int nroots, int use_graph,
+ * adc_davidson returns it; the message of a failed system is its context's
+ * adc_last_error); stats: host [3] or NULL: lockstep iterations (concurrent:
+ * the largest iteration count), sigma graph replays, graph captures.
+ * Returns ADC_OK when every system converged, else the first non-OK status;
+ * ADC_E_ARG for bad arguments (message in adc_last_error(NULL)). */
+int adc_batch_davidson(adc_ctx* const* ctxs, int nsys, int nroots, int flags,
                        double* energies, double* spec_factors, int* n_iter, int* status,
                        long long* stats);
 

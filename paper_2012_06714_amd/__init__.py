@@ -93,8 +93,9 @@ def _dev(x, torch, dtype=None):
     return ctypes.c_void_p(x.data_ptr())
 
 
-def batch_davidson(contexts, nroots, use_graph=True):
-    """Solve several systems together (adc_batch_davidson).  Returns
+def batch_davidson(contexts, nroots, use_graph=True, concurrent=False):
+    """Solve several systems together (adc_batch_davidson): in lockstep, or
+    concurrently on host threads (concurrent=True).  Returns
     (energies [nsys][nroots], P [nsys][nroots], iterations [nsys],
     statuses [nsys], stats {iterations, graph_launches, captures})."""
     import numpy as np
@@ -106,7 +107,7 @@ def batch_davidson(contexts, nroots, use_graph=True):
     it = np.zeros(n, dtype=np.int32)
     st = np.zeros(n, dtype=np.int32)
     stats = np.zeros(3, dtype=np.int64)
-    rc = lib.adc_batch_davidson(arr, n, int(nroots), int(bool(use_graph)),
+    rc = lib.adc_batch_davidson(arr, n, int(nroots), int(bool(use_graph)) | (2 if concurrent else 0),
                                 e.ctypes.data_as(ctypes.c_void_p), P.ctypes.data_as(ctypes.c_void_p),
                                 it.ctypes.data_as(ctypes.c_void_p), st.ctypes.data_as(ctypes.c_void_p),
                                 stats.ctypes.data_as(ctypes.c_void_p))

@@ -64,6 +64,10 @@ struct DBuf {
     ~DBuf() { release(); }
     void swap(DBuf& o) noexcept { std::swap(p, o.p); std::swap(n, o.n); std::swap(arena, o.arena); }
     void alloc(size_t count, Arena* a);
+    // at least `count` elements, reallocating only to grow (contents lost then)
+    void ensure(size_t count, Arena* a) {
+        if (n < count) alloc(count, a);
+    }
     void release();
     T* get() const { return p; }
     size_t bytes() const { return n * sizeof(T); }

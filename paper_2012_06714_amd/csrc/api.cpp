@@ -1,6 +1,8 @@
 // C ABI entry points: host-side argument validation, error capture, and the
 // mapping of C++ exceptions to status codes.
+#include <algorithm>
 #include <cmath>
+#include <vector>
 #include <cstring>
 #include <string>
 
@@ -105,7 +107,8 @@ int adc_set_option(adc_ctx* c, const char* key, double value) {
         if (value <= 0) return fail(c, ADC_E_ARG, "tol_r must be > 0");
         c->tol_r = value;
     } else if (k == "verbose") {
-        c->verbose = value != 0;
+        if (value < 0 || value > 2) return fail(c, ADC_E_ARG, "verbose: 0, 1 or 2");
+        c->verbose = (int)value;
     } else if (k == "graph") {
         // 1: replay sigma from a captured HIP graph per (vector count, precision)
         if (value != 0 && value != 1) return fail(c, ADC_E_ARG, "graph: 0 or 1");
@@ -368,10 +371,10 @@ int adc_mlp_adam(adc_ctx* c, float* params, const float* grad, float* m, float* 
     });
 }
 
-int adc_batch_davidson(adc_ctx* const* ctxs, int nsys, int nroots, int use_graph,
+int adc_batch_davidson(adc_ctx* const* ctxs, int nsys, int nroots, int flags,
                        double* energies, double* spec_factors, int* n_iter, int* status,
                        long long* stats) {
-    if (!ctxs || nsys < 1 || nroots < 1 || !energies)
+    if (!ctxs || nsys < 1 || nroots < 1 || !energies || flags < 0 || flags > 3)
         return fail(nullptr, ADC_E_ARG, "adc_batch_davidson: bad arguments");
     for (int k = 0; k < nsys; ++k) {
         if (!ctxs[k]) return fail(nullptr, ADC_E_ARG, "adc_batch_davidson: NULL context");
@@ -381,9 +384,37 @@ int adc_batch_davidson(adc_ctx* const* ctxs, int nsys, int nroots, int use_graph
             if (ctxs[j] == ctxs[k])
                 return fail(nullptr, ADC_E_ARG, "adc_batch_davidson: a context appears twice");
     }
+    const bool use_graph = (flags & 1) != 0;
+    if (flags & 2) {
+        return guarded(nullptr, [&]() {
+            const long long l0 = [&]() {
+                long long n = 0;
+                for (int k = 0; k < nsys; ++k) n += ctxs[k]->graph_launches;
+                return n;
+            }();
+            long long c0 = 0;
+            for (int k = 0; k < nsys; ++k) c0 += ctxs[k]->graph_captures;
+            std::vector<int> its(nsys);
+            int rc = adc::batch_concurrent(ctxs, nsys, nroots, use_graph, 8, energies,
+                                           spec_factors, its.data(), status);
+            if (n_iter)
+                for (int k = 0; k < nsys; ++k) n_iter[k] = its[k];
+            if (stats) {
+                long long l1 = 0, c1 = 0;
+                for (int k = 0; k < nsys; ++k) {
+                    l1 += ctxs[k]->graph_launches;
+                    c1 += ctxs[k]->graph_captures;
+                }
+                stats[0] = *std::max_element(its.begin(), its.end());
+                stats[1] = l1 - l0;
+                stats[2] = c1 - c0;
+            }
+            return rc;
+        });
+    }
     return guarded(nullptr, [&]() {
         adc::BatchStats st;
-        int rc = adc::batch_davidson(ctxs, nsys, nroots, use_graph != 0, energies, spec_factors,
+        int rc = adc::batch_davidson(ctxs, nsys, nroots, use_graph, energies, spec_factors,
                                      n_iter, status, &st);
         if (stats) {
             stats[0] = st.iterations;

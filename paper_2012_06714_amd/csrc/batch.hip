@@ -1,13 +1,15 @@
 // Several independent systems (contexts) solved together: the Davidson
 // solvers advance in lockstep, and each iteration applies sigma to the new
-// trial vectors of every active system in one HIP graph launch.  The graph
-// holds one branch per system (spread over a few streams, so unequal systems
-// run side by side); it is captured after an eager warm-up of every branch and
-// reused for as long as the set of (system, vector count, precision) and the
-// scratch buffers of its contexts stay the same.  Trial vectors enter and
-// results leave through each context's fixed graph buffers.
+// trial vectors of every active system as replays of that system's captured
+// sigma graphs (one per vector count and precision, kept by the context),
+// issued back to back over a few streams so that unequal systems run side by
+// side.  Per-system graphs are captured a handful of times per solve; a
+// single graph over the whole active set would have to be captured again
+// whenever any system converges or changes its number of new vectors.
 #include "context.hpp"
 
+#include <atomic>
+#include <thread>
 #include <vector>
 
 namespace adc {
@@ -15,20 +17,6 @@ namespace adc {
 namespace {
 
 constexpr int NSTREAM = 4;    // branch streams (default priority)
-
-struct BatchGraph {
-    std::vector<long long> key;                                   // (system, nvec, precision)...
-    std::vector<std::map<int, std::pair<void*, size_t>>> slots;  // scratch per branch
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    ~BatchGraph() { drop(); }
-    void drop() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        exec = nullptr;
-        graph = nullptr;
-    }
-};
 
 struct Streams {
     hipStream_t main = nullptr;
@@ -85,7 +73,6 @@ int batch_davidson(adc_ctx* const* ctx, int nsys, int nroots, bool use_graph, do
     } cleanup{sol};
     for (int k = 0; k < nsys; ++k) sol[k] = solver_new(ctx[k], nroots);
     Streams S;
-    BatchGraph G;
     std::vector<const double*> X(nsys);
     std::vector<double*> W(nsys);
     std::vector<int> nn(nsys), prec(nsys), active;
@@ -98,83 +85,43 @@ int batch_davidson(adc_ctx* const* ctx, int nsys, int nroots, bool use_graph, do
         if (!use_graph) {
             for (int k : active) sigma(ctx[k], X[k], W[k], nn[k], prec[k]);
         } else {
-            std::vector<long long> key;
-            for (int k : active) {
-                key.push_back(k);
-                key.push_back(nn[k]);
-                key.push_back(prec[k]);
-                adc_ctx* c = ctx[k];
-                const size_t need = (size_t)nn[k] * c->dim;
-                if (c->Xg.n < need) {
-                    G.drop();
-                    drop_graphs(c);
-                    c->Xg.alloc(need, &c->arena);
-                    c->Yg.alloc(need, &c->arena);
-                }
-            }
-            bool valid = G.exec && G.key == key;
-            for (size_t b = 0; valid && b < active.size(); ++b)
-                valid = ctx[active[b]]->E.scratch.still_valid(G.slots[b]);
-            // trial vectors in: the main stream waits for each system's own stream
+            // each active system replays its own sigma graph (captured per
+            // vector count and precision), the systems dealt round-robin to
+            // the branch streams so that unequal ones run side by side; each
+            // branch waits for its system's stream and the system's stream
+            // waits for the branch
+            int b = 0;
             for (int k : active) {
                 adc_ctx* c = ctx[k];
+                hipStream_t br = S.br[b++ % NSTREAM];
                 ADC_HIP(hipEventRecord(S.sync, c->E.stream));
-                ADC_HIP(hipStreamWaitEvent(S.main, S.sync, 0));
-                ADC_HIP(hipMemcpyAsync(c->Xg.p, X[k], (size_t)nn[k] * c->dim * sizeof(double),
-                                       hipMemcpyDeviceToDevice, S.main));
-            }
-            if (!valid) {
-                G.drop();
-                // warm-up: every branch once, eagerly (allocations, tile tuning)
-                for (int k : active) {
-                    StreamSwap sw(ctx[k]->E, S.main);
-                    sigma_eager(ctx[k], ctx[k]->Xg.p, ctx[k]->Yg.p, nn[k], prec[k]);
-                }
-                ADC_HIP(hipStreamSynchronize(S.main));
-                G.slots.assign(active.size(), {});
-                ADC_HIP(hipStreamBeginCapture(S.main, hipStreamCaptureModeThreadLocal));
-                try {
-                    ADC_HIP(hipEventRecord(S.fork, S.main));
-                    for (auto& b : S.br) ADC_HIP(hipStreamWaitEvent(b, S.fork, 0));
-                    for (size_t b = 0; b < active.size(); ++b) {
-                        adc_ctx* c = ctx[active[b]];
-                        StreamSwap sw(c->E, S.br[b % NSTREAM]);
-                        c->E.autotune = false;
-                        c->E.scratch.touched = &G.slots[b];
-                        sigma_eager(c, c->Xg.p, c->Yg.p, nn[active[b]], prec[active[b]]);
+                ADC_HIP(hipStreamWaitEvent(br, S.sync, 0));
+                const long long cap0 = c->graph_captures;
+                {
+                    StreamSwap sw(c->E, br);
+                    const bool ug = c->use_graph;
+                    c->use_graph = true;
+                    try {
+                        sigma(c, X[k], W[k], nn[k], prec[k]);
+                    } catch (...) {
+                        c->use_graph = ug;
+                        throw;
                     }
-                    for (int b = 0; b < NSTREAM; ++b) {
-                        ADC_HIP(hipEventRecord(S.join[b], S.br[b]));
-                        ADC_HIP(hipStreamWaitEvent(S.main, S.join[b], 0));
-                    }
-                } catch (...) {
-                    hipGraph_t dead = nullptr;
-                    (void)hipStreamEndCapture(S.main, &dead);
-                    if (dead) (void)hipGraphDestroy(dead);
-                    throw;
+                    c->use_graph = ug;
                 }
-                ADC_HIP(hipStreamEndCapture(S.main, &G.graph));
-                ADC_HIP(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
-                G.key = key;
-                if (st) st->captures++;
+                ADC_HIP(hipEventRecord(S.sync, br));
+                ADC_HIP(hipStreamWaitEvent(c->E.stream, S.sync, 0));
+                if (st) {
+                    st->graph_launches += (nn[k] + 63) / 64;
+                    st->captures += c->graph_captures - cap0;
+                }
             }
-            ADC_HIP(hipGraphLaunch(G.exec, S.main));
-            if (st) st->graph_launches++;
-            // results out; each system's stream waits for them
-            for (int k : active) {
-                adc_ctx* c = ctx[k];
-                ADC_HIP(hipMemcpyAsync(W[k], c->Yg.p, (size_t)nn[k] * c->dim * sizeof(double),
-                                       hipMemcpyDeviceToDevice, S.main));
-            }
-            ADC_HIP(hipEventRecord(S.ready, S.main));
-            for (int k : active) ADC_HIP(hipStreamWaitEvent(ctx[k]->E.stream, S.ready, 0));
         }
         for (int k : active) {
             // a solver whose space changed shape frees scratch only at its end
             solver_advance(sol[k]);
         }
     }
-    G.drop();
     int worst = ADC_OK;
     for (int k = 0; k < nsys; ++k) {
         int it = 0;
@@ -183,6 +130,61 @@ int batch_davidson(adc_ctx* const* ctx, int nsys, int nroots, bool use_graph, do
         if (n_iter) n_iter[k] = it;
         if (status) status[k] = s;
         if (s != ADC_OK && worst == ADC_OK) worst = s;
+    }
+    return worst;
+}
+
+// The same systems solved concurrently instead of in lockstep: up to
+// `nthreads` host threads each take the next unsolved system and run the
+// single-system solver on it, on a stream of its own when the context is
+// bound to the null stream.  The host work of one solve (its small
+// eigenproblems, the synchronisations that read residual norms back) then
+// overlaps the device work of the others.
+int batch_concurrent(adc_ctx* const* ctx, int nsys, int nroots, bool use_graph, int nthreads,
+                     double* energies, double* P, int* n_iter, int* status) {
+    std::atomic<int> next{0};
+    std::vector<int> st(nsys, ADC_OK), its(nsys, 0);
+    auto solve = [&](int k) {
+        adc_ctx* c = ctx[k];
+        const hipStream_t old = c->E.stream;
+        hipStream_t mine = nullptr;
+        const bool ug = c->use_graph;
+        try {
+            if (!old) {
+                ADC_HIP(hipStreamCreate(&mine));
+                c->E.stream = mine;
+                ADC_BLAS(rocblas_set_stream(c->E.blas, mine));
+            }
+            c->use_graph = use_graph;
+            st[k] = davidson(c, nroots, energies + (size_t)k * nroots,
+                             P ? P + (size_t)k * nroots : nullptr, nullptr, &its[k]);
+        } catch (const Error& e) {
+            st[k] = e.code;
+            c->err = e.what();
+        } catch (const std::exception& e) {
+            st[k] = ADC_E_HIP;
+            c->err = e.what();
+        }
+        c->use_graph = ug;
+        if (mine) {
+            (void)hipStreamSynchronize(mine);
+            c->E.stream = old;
+            (void)rocblas_set_stream(c->E.blas, old);
+            (void)hipStreamDestroy(mine);
+        }
+    };
+    const int nt = std::max(1, std::min(nthreads, nsys));
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nt; ++t)
+        pool.emplace_back([&]() {
+            for (int k = next++; k < nsys; k = next++) solve(k);
+        });
+    for (auto& t : pool) t.join();
+    int worst = ADC_OK;
+    for (int k = 0; k < nsys; ++k) {
+        if (n_iter) n_iter[k] = its[k];
+        if (status) status[k] = st[k];
+        if (st[k] != ADC_OK && worst == ADC_OK) worst = st[k];
     }
     return worst;
 }

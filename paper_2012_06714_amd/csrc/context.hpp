@@ -81,6 +81,7 @@ struct adc_ctx {
     std::vector<SigmaGraph> graphs;
     adc::DBuf<double> Xg, Yg;     // the captured graphs' input and output
     long long graph_launches = 0;
+    long long graph_captures = 0;
 
     // learned preconditioner (mlp.hip): installed parameters, or diagonal
     double escale = 1.0;                  // max |eps|, the feature energy scale
@@ -159,6 +160,8 @@ struct BatchStats {
 };
 int batch_davidson(adc_ctx* const* ctx, int nsys, int nroots, bool use_graph, double* energies,
                    double* P, int* n_iter, int* status, BatchStats* st);
+int batch_concurrent(adc_ctx* const* ctx, int nsys, int nroots, bool use_graph, int nthreads,
+                     double* energies, double* P, int* n_iter, int* status);
 struct Solver;   // one solve as a state machine (batched driving in batch.hip)
 Solver* solver_new(adc_ctx* c, int nroots);
 void solver_delete(Solver* s);

@@ -7,8 +7,10 @@
 // Parameters follow this reading of the method:
 //   guesses: unit vectors at the `block` smallest diagonal entries (ties to the
 //            lower index) or the vectors given by adc_set_guess;
-//   converged when every root k < nroots has |theta_k - theta_k(prev)| <= tol_e
-//            and ||r_k|| <= tol_r max(1, |theta_k|) (the residual bound is
+//   converged when every root k < nroots has |theta_k - theta_k(prev)| <=
+//            max(tol_e, 8 eps |theta_k|) (eps the FP64 unit roundoff: no
+//            change below the resolution of theta is meaningful) and
+//            ||r_k|| <= tol_r max(1, |theta_k|) (the residual bound is
 //            relative for roots beyond 1 Eh, absolute otherwise);
 //   correction d = r / (theta - D) with |theta - D| floored at 1e-8, or the
 //            learned correction of it (mlp.hip) when a network is installed;
@@ -27,6 +29,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <chrono>
 #include <cmath>
 #include <numeric>
@@ -119,7 +122,7 @@ struct Dav {
     Engine& E;
     long long dim;
     int block, max_space;
-    DBuf<double> V, W, X, AX, R, D, G, S, th, ev_e, part, rn, cmat;
+    DBuf<double> V, W, X, AX, R, D, G, S, th, ev_e, part, rn, cmat, tmp, gb;
     DBuf<int> sel_d, info;
     int nchunk = 0;
 
@@ -128,8 +131,8 @@ struct Dav {
     void rownorms(const double* M, int nrow, std::vector<double>& out) {
         nchunk = (int)std::min<long long>(256, (dim + 4095) / 4096);
         if (nchunk < 1) nchunk = 1;
-        part.alloc((size_t)nrow * nchunk, &c->arena);
-        rn.alloc(nrow, &c->arena);
+        part.ensure((size_t)nrow * nchunk, &c->arena);
+        rn.ensure(nrow, &c->arena);
         hipLaunchKernelGGL(k_rownorm_part, dim3(nchunk, nrow), dim3(256), 0, E.stream, M, dim,
                            nchunk, part.p);
         hipLaunchKernelGGL(k_rownorm_final, dim3((nrow + 63) / 64), dim3(64), 0, E.stream, part.p,
@@ -149,7 +152,7 @@ struct Dav {
     // of unit norm that are numerically dependent on V or on each other) are
     // dropped.  The kept rows are compacted to the front; returns their count.
     int orthonormalize(double* Dm, int nd, int m) {
-        cmat.alloc((size_t)std::max(1, nd * std::max(m, nd)), &c->arena);
+        cmat.ensure((size_t)std::max(1, nd * std::max(m, nd)), &c->arena);
         std::vector<double> nrm;
         rownorms(Dm, nd, nrm);
         for (int k = 0; k < nd; ++k) {
@@ -158,8 +161,7 @@ struct Dav {
                                Dm + (size_t)k * dim, s, dim);
         }
         ADC_HIP(hipGetLastError());
-        DBuf<double> tmp;
-        tmp.alloc((size_t)nd * dim, &c->arena);
+        tmp.ensure((size_t)nd * dim, &c->arena);
         std::vector<double> G, T;
         for (int pass = 0; pass < 2 && nd > 0; ++pass) {
             if (m > 0) {
@@ -270,6 +272,15 @@ struct Solver {
     bool mixed, use_mlp, done = false;
     double best_mixed_r = INFINITY, best_mlp_r = INFINITY;
     int stall = 0, mlp_stall = 0;
+    // wall seconds per phase (verbose >= 2): sigma (timed by the driver), the
+    // new rows of V W^T, eigenpairs + Ritz vectors + residuals, the rest
+    double ph[4] = {0, 0, 0, 0};
+    clk::time_point tp;
+    void lap(int k) {
+        const auto now = clk::now();
+        ph[k] += std::chrono::duration<double>(now - tp).count();
+        tp = now;
+    }
 
     Solver(adc_ctx* cc, int nr) : c(cc), E(cc->E), nroots(nr), dim(cc->dim), d(cc) {
         t0 = clk::now();
@@ -368,6 +379,10 @@ struct Solver {
     // vector.  Returns false once the solve has ended.
     bool request(const double** X, double** W, int* nn, int* precision) {
         if (done) return false;
+        if (c->verbose >= 2) {
+            ADC_HIP(hipStreamSynchronize(E.stream));
+            tp = clk::now();
+        }
         *X = d.V.p + (size_t)newstart * dim;
         *W = d.W.p + (size_t)newstart * dim;
         *nn = m - newstart;
@@ -377,20 +392,25 @@ struct Solver {
 
     // everything after the sigma products; returns true when the solve ended
     bool advance() {
+        if (c->verbose >= 2) {
+            ADC_HIP(hipStreamSynchronize(E.stream));
+            lap(0);
+        }
         ++it;
         const int nn = m - newstart;
         c->st_sigvec += nn;
         if (mixed) c->st_mixed++;
         // G rows for the new vectors: blk[nn][m] = W_new V^T
         {
-            DBuf<double> gb;
-            gb.alloc((size_t)nn * m, &c->arena);
+            DBuf<double>& gb = d.gb;
+            gb.ensure((size_t)nn * m, &c->arena);
             gemm_rm<double>(E, false, true, nn, m, dim, 1.0, d.W.p + (size_t)newstart * dim, dim, 0,
                             d.V.p, dim, 0, 0.0, gb.p, m, 0, 1);
             blk.resize((size_t)nn * m);
             ADC_HIP(hipMemcpyAsync(blk.data(), gb.p, blk.size() * sizeof(double),
                                    hipMemcpyDeviceToHost, E.stream));
             ADC_HIP(hipStreamSynchronize(E.stream));
+            if (c->verbose >= 2) lap(1);
             for (int k = 0; k < nn; ++k) {
                 const int r = newstart + k;
                 for (int j = 0; j < newstart; ++j) {
@@ -426,6 +446,7 @@ struct Solver {
                            d.AX.p, d.X.p, d.th.p, d.R.p, dim, nbk);
         ADC_HIP(hipGetLastError());
         d.rownorms(d.R.p, nbk, rnorm);
+        if (c->verbose >= 2) lap(2);
         for (int k = 0; k < nbk; ++k)
             if (!std::isfinite(rnorm[k]) || !std::isfinite(theta[k]))
                 throw Error(ADC_E_NUMERIC, "non-finite Ritz value or residual");
@@ -444,10 +465,15 @@ struct Solver {
             c->rec_root.push_back(k);
             ++c->nrec;
         }
-        // residuals in units of max(1, |theta|): relative for large roots
+        // residuals in units of max(1, |theta|): relative for large roots;
+        // eigenvalue changes against tol_e, or against the FP64 resolution of
+        // theta (8 ulp) where that is coarser: changes below it are rounding
         double maxde = 0.0, maxr = 0.0;
+        bool e_ok = true;
         for (int k = 0; k < nroots; ++k) {
-            maxde = std::max(maxde, std::fabs(theta[k] - theta_old[k]));
+            const double de = std::fabs(theta[k] - theta_old[k]);
+            maxde = std::max(maxde, de);
+            e_ok = e_ok && de <= std::max(tol_e, 8.0 * DBL_EPSILON * std::fabs(theta[k]));
             maxr = std::max(maxr, rnorm[k] / std::max(1.0, std::fabs(theta[k])));
         }
         if (c->verbose) {
@@ -471,7 +497,7 @@ struct Solver {
             std::fill(theta_old.begin(), theta_old.end(), INFINITY);
             return false;
         }
-        if (!mixed && maxde <= tol_e && maxr <= tol_r) return end(ADC_OK);
+        if (!mixed && e_ok && maxr <= tol_r) return end(ADC_OK);
         if (it >= c->max_iter) return end(ADC_E_NOCONV);
         for (int k = 0; k < nbk; ++k) theta_old[k] = theta[k];
         std::vector<int> sel;
@@ -523,6 +549,7 @@ struct Solver {
                                (size_t)kept * dim * sizeof(double), hipMemcpyDeviceToDevice,
                                E.stream));
         m += kept;
+        if (c->verbose >= 2) lap(3);
         return false;
     }
 
@@ -533,6 +560,10 @@ struct Solver {
     }
 
     int finish(double* energies, double* P, double* vecs, int* n_iter) {
+        if (c->verbose >= 2 && it > 0)
+            fprintf(stderr, "adc_davidson phases per iteration (ms): sigma %.3f, V W^T rows %.3f, "
+                    "eigenpairs+Ritz+residuals %.3f, preconditioner+orthonormalisation %.3f\n",
+                    1e3 * ph[0] / it, 1e3 * ph[1] / it, 1e3 * ph[2] / it, 1e3 * ph[3] / it);
         if (c->use_mlp && !use_mlp) c->mlp_fallbacks++;
         for (int k = 0; k < nroots; ++k) energies[k] = theta[k];
         if (vecs)

@@ -140,6 +140,13 @@ void setup_all(adc_ctx* c, const double* eps, const double* B) {
         if (c->order == 2) c->Bvv.release();   // IP-ADC(2) never reads the vv block
     }
 
+    // ADC(2) needs the (ov|ov) and (oo|ov) blocks only for the amplitudes and
+    // M11 above: free them (a batch of systems keeps many contexts resident)
+    if (c->order == 2) {
+        c->ovov.release();
+        c->ooov.release();
+    }
+
     // ---- exact diagonal -------------------------------------------------------
     c->diag.alloc((size_t)c->dim, &c->arena);
     set_diag(E, c->diag.p, c->M11.p, n1);

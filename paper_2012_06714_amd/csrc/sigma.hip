@@ -490,6 +490,7 @@ static void sigma_graph(adc_ctx* c, const double* X, double* Y, int nvec, int pr
             c->graphs.emplace_back();
             g = &c->graphs.back();
         }
+        ++c->graph_captures;
         g->nvec = nvec;
         g->precision = precision;
         g->slots = used;
