@@ -475,11 +475,17 @@ static void launch_tiles(hipStream_t st, bool ta, bool tb, const TI* A, const TI
 //   0: 64x64 (4x1)    1: 128x128 (2x2)   2: 128x128 (4x2)   3: 128x64 (2x2)
 //   4: 256x128 (2x2)  5: 256x256 (2x2)   6: 256x128 (4x2)   7: 256x256 (4x2)
 // The 8-wave 256x256 tile gives each wave a 64x128 block: half the LDS reads
-// per multiply of the 64x64 blocks, which is what limits BF16.
+// per multiply of the 64x64 blocks, which is what limits BF16. For FP64
+// the 4-wave 64x64 tile (four workgroups per CU) beats larger tiles on
+// products with few rows and a long summed index, such as the 320-row
+// particle-particle contraction: occupancy hides more latency than the larger
+// tiles save in operand reads.
 
 // configurations compiled for each compute type (the rest fall back to 0)
 template <typename T> static bool cfg_available(int cfg);
-template <> inline bool cfg_available<double>(int cfg) { return cfg == 0 || cfg == 2 || cfg == 3; }
+template <> inline bool cfg_available<double>(int cfg) {
+    return cfg == 0 || cfg == 2 || cfg == 3;
+}
 template <> inline bool cfg_available<float>(int cfg) { return cfg == 0 || cfg == 1 || cfg == 2; }
 template <> inline bool cfg_available<bf16_t>(int cfg) {
     return cfg == 0 || cfg == 1 || cfg == 6 || cfg == 7;
