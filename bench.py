@@ -30,6 +30,10 @@ PEAKS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 # counter runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, the factors of a plain
 # 1 GiB copy), summarised in profiles/pp_term_ea_adc3_o20v180_hbm_bytes.md.
 # Valid for the kernels as measured; re-measure whenever they change.
+# sigma levels: FP64; BF16 products (FP32 storage) with FP64 refinement in
+# the solver; FP32 products, used by the solver as a middle phase (BF16 ->
+# FP32 -> FP64)
+LEVEL = {"fp64": 0, "mixed": 1, "mixed3": 2}
 PP_TRAFFIC = {("ea-adc3-o20v180", "fp64"): 4.9786e+10, ("ea-adc3-o20v180", "mixed"): 7.3463e+09}
 HBM_GBPS = 8000.0
 
@@ -161,7 +165,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2")
-    ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
+    ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed", "mixed3"])
     ap.add_argument("--no-davidson", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tune-log", action="store_true", help="log the GEMM autotuner's choices")
@@ -214,7 +218,7 @@ def main():
     f_total, f_pp = ctx.sigma_flops(nvec)
 
     def time_sigma(prec):
-        ctx.set_option("precision", 1 if prec == "mixed" else 0)
+        ctx.set_option("precision", LEVEL[prec])
         for _ in range(args.warmup):
             ctx.sigma(X, out=Y)
         torch.cuda.synchronize()
@@ -230,7 +234,7 @@ def main():
         return dt, float(np.mean(pp))
 
     def solve(prec, e_ref=None):
-        ctx.set_option("precision", 1 if prec == "mixed" else 0)
+        ctx.set_option("precision", LEVEL[prec])
         ctx.set_option("block", wl.block)
         ctx.set_option("tol_e", 1e-7)
         ctx.set_option("tol_r", 1e-7)
@@ -248,7 +252,7 @@ def main():
         scaled_r = np.max(rn / np.maximum(1.0, np.abs(th)), axis=1)
         for k in range(0, len(tsec), max(1, len(tsec) // 25)):
             log(f"  {prec} it {k + 1:4d} t {tsec[k]:7.3f} s  max|theta-ref| {err[k]:.3e}  "
-                f"max r/max(1,|theta|) {scaled_r[k]:.3e}  {'mixed' if mx[k] else 'fp64'}")
+                f"max r/max(1,|theta|) {scaled_r[k]:.3e}  {('fp64', 'bf16', 'fp32')[int(mx[k])]}")
         log(f"bench: {prec} davidson {it} it ({st['mixed_iters']} mixed), {t_dav:.2f} s, "
             f"time-to-1e-6 {t_1e6}")
         return {"converged": bool(conv), "iterations": it, "mixed_iterations": st["mixed_iters"],
@@ -257,22 +261,24 @@ def main():
                 "max_abs_error_vs_fp64_Eh": float(np.max(np.abs(np.array(e) - ref)))}
 
     runs = {}
-    for prec in ("fp64", "mixed"):
+    for prec in ("fp64", "mixed", "mixed3"):
         dt, ms_pp = time_sigma(prec)
         runs[prec] = {"ms_per_step": dt * 1e3, "sigma_tflops": f_total / dt / 1e12,
                       "pp_ms_per_launch": ms_pp}
+    runs["mixed3"]["sigma_products"] = "fp32"
     if not args.no_davidson:
         runs["fp64"]["davidson"] = solve("fp64")
         e_ref = runs["fp64"]["davidson"]["energies"]
-        runs["mixed"]["davidson"] = solve("mixed", e_ref)
-        runs["mixed"]["davidson"]["error_per_root_Eh"] = list(
-            np.abs(np.array(runs["mixed"]["davidson"]["energies"]) - np.array(e_ref)))
+        for prec in ("mixed", "mixed3"):
+            runs[prec]["davidson"] = solve(prec, e_ref)
+            runs[prec]["davidson"]["error_per_root_Eh"] = list(
+                np.abs(np.array(runs[prec]["davidson"]["energies"]) - np.array(e_ref)))
 
     main_run = runs[precision]
     dt = main_run["ms_per_step"] / 1e3
     tflops = main_run["sigma_tflops"]
     ms_pp = main_run["pp_ms_per_launch"]
-    dtype_key = "fp64" if precision == "fp64" else "bf16"
+    dtype_key = {"fp64": "fp64", "mixed": "bf16", "mixed3": "fp32"}[precision]
     achieved = f_pp / (ms_pp / 1e3) / 1e12 if ms_pp > 0 else None
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAKS_TFLOPS[dtype_key],
                 "unit": "TFLOP/s",
@@ -281,7 +287,7 @@ def main():
                 "kernel": "particle-particle term: (ac|bd) slab rebuild + contraction "
                           "(k_gemm kinds 1 and 2)",
                 "ms_per_launch": ms_pp, "flops_per_launch": f_pp}
-    extra = {"fp64": runs["fp64"], "mixed": runs["mixed"]}
+    extra = {"fp64": runs["fp64"], "mixed": runs["mixed"], "mixed3": runs["mixed3"]}
 
     cpu = None
     if not args.no_cpu:
@@ -303,7 +309,7 @@ def main():
         "metric": "EA-ADC(3) sigma TFLOP/s + Davidson time-to-1e-6 Eh, mixed vs FP64 on 1 GPU",
         "value": tflops, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if precision == "fp64" else "bf16",
+        "scaling": "weak", "vs_baseline": None, "dtype": {"fp64": "f64", "mixed": "bf16", "mixed3": "f32"}[precision],
         "data": "synthetic",
         "config": {"workload": wl.name, "kind": wl.kind, "order": wl.order, "nocc": wl.nocc,
                    "nvir": wl.nvir, "naux": wl.naux, "trial_vectors": nvec, "dim": ctx.dim,

@@ -82,9 +82,12 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
               int order, int kind, adc_ctx** out);
 
 /* Options (numeric values):
- *   "precision"   0 = FP64 sigma (default), 1 = mixed: sigma contractions in
- *                 reduced precision with FP32 accumulation, FP64 subspace,
- *                 then FP64 refinement iterations
+ *   "precision"   0 = FP64 sigma (default); 1 = mixed: sigma contractions
+ *                 with BF16 products and FP32 sums (FP32 storage), FP64
+ *                 subspace, then FP64 refinement iterations; 2 = as 1 with a
+ *                 phase of FP32 products (FP32 storage and sums) between the
+ *                 BF16 and FP64 phases.  adc_sigma runs at the selected level
+ *                 (2: FP32 products)
  *   "block"       trial vectors per sigma launch in adc_davidson (default:
  *                 max(nroots, 8))
  *   "max_space"   Davidson subspace limit (default 8 * block)
@@ -163,8 +166,9 @@ int adc_set_guess(adc_ctx* ctx, const double* V0, int nvec);
 /* Convergence history of the last adc_davidson call: for each iteration k <
  * min(count, max_entries): seconds[k] since the call started (host wall
  * clock after the iteration's Ritz values were known), theta[k*nroots + r]
- * and rnorm[k*nroots + r] for the lowest nroots Ritz pairs, and mixed[k] = 1
- * for a reduced-precision iteration.  Any output may be NULL.  Returns the
+ * and rnorm[k*nroots + r] for the lowest nroots Ritz pairs, and mixed[k] =
+ * the sigma level of the iteration (0 FP64, 1 BF16 products, 2 FP32
+ * products).  Any output may be NULL.  Returns the
  * number of recorded iterations (>= 0) or a negative error code. */
 int adc_history(const adc_ctx* ctx, int max_entries, double* seconds, double* theta,
                 double* rnorm, int* mixed);

@@ -89,7 +89,8 @@ int adc_set_option(adc_ctx* c, const char* key, double value) {
     std::string k(key);
     if (!std::isfinite(value)) return fail(c, ADC_E_ARG, "adc_set_option: value not finite");
     if (k == "precision") {
-        if (value != 0 && value != 1) return fail(c, ADC_E_ARG, "precision must be 0 or 1");
+        if (value != 0 && value != 1 && value != 2)
+            return fail(c, ADC_E_ARG, "precision must be 0, 1 or 2");
         c->precision = (int)value;
     } else if (k == "block") {
         if (value < 0 || value > 4096) return fail(c, ADC_E_ARG, "block out of range");

@@ -63,7 +63,9 @@ struct adc_ctx {
         // as the FP32 copies are when staged) and FP32 G
         adc::DBuf<adc::bf16_t> httT1, httT2, htT1, htD, hoovvT, htT, hovov;
         adc::DBuf<float> fG;
-        bool ready = false, ready_mixed = false;
+        // FP32 copies for the FP32-product level
+        adc::DBuf<float> fttT1, fttT2, ftT1, ftD, foovvT, ftT;
+        bool ready = false, ready_mixed = false, ready_f32 = false;
     } eal;
     long long pp_slab_bytes = 4LL << 30;   // rebuilt four-index slab (particle-particle term)
     int pp_blocks = 0;                     // minimum number of a-blocks of that term (0: automatic)
@@ -115,7 +117,7 @@ void build_mixed(adc_ctx* c);
 void setup_adc3(adc_ctx* c, const double* tt, const double* X1);
 
 // sigma.hip
-template <typename T>
+template <typename T, typename TB>
 void sigma_block(adc_ctx* c, const double* X, double* Y, int nvec);
 
 // vvvv.hip: out[x][a][b] = sum_cd (ac|bd) in[x][c][d], (ac|bd) rebuilt from B_vv
@@ -127,8 +129,9 @@ void drop_graphs(adc_ctx* c);
 void sigma_cost(const adc_ctx* c, int nvec, double* total, double* pp);
 
 // ea_layout.hip
-bool ea_layout_use(adc_ctx* c, bool mixed);     // arranged EA sigma path for this call?
-void ea_layout_build(adc_ctx* c, bool mixed);   // make the arranged operands (once each)
+// level: 0 FP64, 1 BF16 products, 2 FP32 products
+bool ea_layout_use(adc_ctx* c, int level);      // arranged EA sigma path for this call?
+void ea_layout_build(adc_ctx* c, int level);    // make the arranged operands (once each)
 // P1[z][x][j][y] = Y[z][j][x][y], P2[z][x][j][y] = Y[z][j][y][x],
 // D = P2 - 2 P1, Pm = 2 P1 - P2 (storage TB), Dw = D (storage T); null outputs skipped
 template <typename T, typename TB>

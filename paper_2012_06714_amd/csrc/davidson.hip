@@ -19,11 +19,13 @@
 //            two passes; directions whose Gram eigenvalue falls below
 //            max(1e-20, 1e-14 lambda_max) are dropped;
 //   restart to the current `block` Ritz vectors when V would exceed max_space.
-// Mixed precision ("precision" = 1): sigma runs in reduced precision until the
+// Mixed precision ("precision" = 1): sigma runs with BF16 products until the
 // (scaled) residuals fall below max(sqrt(tol_r), 1e-3) or 3e-3, or stop
 // decreasing; the space is then rebuilt from the Ritz vectors with FP64 sigma
 // and the iteration continues in FP64 to the requested tolerance (iterative
-// refinement of the reduced-precision subspace).
+// refinement of the reduced-precision subspace).  "precision" = 2 inserts a
+// phase with FP32 products between the two, left at scaled residuals of
+// max(tol_r, 2e-6) or when they stop halving for three iterations.
 #include "context.hpp"
 
 #include <rocsolver/rocsolver.h>
@@ -263,13 +265,14 @@ struct Solver {
     int nroots;
     long long dim;
     int block, max_space;
-    double tol_e, tol_r, tol_switch;
+    double tol_e, tol_r, tol_switch, tol_switch2;
     const double rel_switch = 3e-3;
     Dav d;
     clk::time_point t0;
     std::vector<double> theta_old, theta, rnorm, Gh, blk;
     int it = 0, status = ADC_OK, m = 0, newstart = 0, nbk = 0;
-    bool mixed, use_mlp, done = false;
+    int stage = 0;    // sigma level of the current phase: 1 BF16, 2 FP32 products, 0 FP64
+    bool use_mlp, done = false;
     double best_mixed_r = INFINITY, best_mlp_r = INFINITY;
     int stall = 0, mlp_stall = 0;
     // wall seconds per phase (verbose >= 2): sigma (timed by the driver), the
@@ -296,6 +299,8 @@ struct Solver {
         // products can resolve, or when they stop falling (three iterations
         // without halving)
         tol_switch = std::max(std::sqrt(tol_r), 1e-3);
+        // and the FP32-product phase at what FP32 sums resolve
+        tol_switch2 = std::max(tol_r, 2e-6);
         d.block = block;
         d.max_space = max_space;
         d.V.alloc((size_t)max_space * dim, &c->arena);
@@ -314,7 +319,7 @@ struct Solver {
         theta_old.assign(block, INFINITY);
         theta.assign(max_space, 0.0);
         Gh.assign((size_t)max_space * max_space, 0.0);
-        mixed = c->precision == 1;
+        stage = c->precision >= 1 ? 1 : 0;
         use_mlp = c->use_mlp && c->mlp_params.p;
         c->st_sigvec = 0;
         c->st_mixed = 0;
@@ -386,7 +391,7 @@ struct Solver {
         *X = d.V.p + (size_t)newstart * dim;
         *W = d.W.p + (size_t)newstart * dim;
         *nn = m - newstart;
-        *precision = mixed ? 1 : 0;
+        *precision = stage;
         return true;
     }
 
@@ -399,7 +404,7 @@ struct Solver {
         ++it;
         const int nn = m - newstart;
         c->st_sigvec += nn;
-        if (mixed) c->st_mixed++;
+        if (stage) c->st_mixed++;
         // G rows for the new vectors: blk[nn][m] = W_new V^T
         {
             DBuf<double>& gb = d.gb;
@@ -455,7 +460,7 @@ struct Solver {
             c->hist_theta.push_back(k < nbk ? theta[k] : NAN);
             c->hist_r.push_back(k < nbk ? rnorm[k] : NAN);
         }
-        c->hist_mixed.push_back(mixed ? 1 : 0);
+        c->hist_mixed.push_back(stage);
         for (int k = 0; k < nroots && k < nbk && c->nrec < c->record_max; ++k) {
             ADC_HIP(hipMemcpyAsync(c->rec_x.p + (size_t)c->nrec * dim, d.X.p + (size_t)k * dim,
                                    dim * sizeof(double), hipMemcpyDeviceToDevice, E.stream));
@@ -478,17 +483,21 @@ struct Solver {
         }
         if (c->verbose) {
             fprintf(stderr, "adc_davidson it %d m %d nbk %d %s max|dE| %.3e max|r| %.3e theta:", it,
-                    m, nbk, mixed ? "mixed" : "fp64", maxde, maxr);
+                    m, nbk, stage == 1 ? "bf16" : stage == 2 ? "fp32" : "fp64", maxde, maxr);
             for (int k = 0; k < nbk; ++k) fprintf(stderr, " %.10f(%.1e)", theta[k], rnorm[k]);
             fprintf(stderr, "\n");
         }
-        if (mixed) {
+        if (stage) {
             stall = (maxr > 0.5 * best_mixed_r) ? stall + 1 : 0;
             best_mixed_r = std::min(best_mixed_r, maxr);
         }
-        if (mixed && (maxr <= tol_switch || maxr <= rel_switch || stall >= 3)) {
-            // FP64 refinement: rebuild the space from the Ritz vectors with FP64 sigma
-            mixed = false;
+        const double sw = stage == 1 ? tol_switch : tol_switch2;
+        if (stage && (maxr <= sw || (stage == 1 && maxr <= rel_switch) || stall >= 3)) {
+            // refinement: the next level (FP32 products after BF16 when asked
+            // for, then FP64) rebuilds the space from the Ritz vectors
+            stage = (stage == 1 && c->precision == 2) ? 2 : 0;
+            stall = 0;
+            best_mixed_r = INFINITY;
             ADC_HIP(hipMemcpyAsync(d.V.p, d.X.p, (size_t)nbk * dim * sizeof(double),
                                    hipMemcpyDeviceToDevice, E.stream));
             m = d.orthonormalize(d.V.p, nbk, 0);
@@ -497,11 +506,11 @@ struct Solver {
             std::fill(theta_old.begin(), theta_old.end(), INFINITY);
             return false;
         }
-        if (!mixed && e_ok && maxr <= tol_r) return end(ADC_OK);
+        if (!stage && e_ok && maxr <= tol_r) return end(ADC_OK);
         if (it >= c->max_iter) return end(ADC_E_NOCONV);
         for (int k = 0; k < nbk; ++k) theta_old[k] = theta[k];
         std::vector<int> sel;
-        double thr = mixed ? tol_switch : tol_r;
+        double thr = stage == 1 ? tol_switch : stage == 2 ? tol_switch2 : tol_r;
         for (int k = 0; k < nbk; ++k)
             if (rnorm[k] > thr * std::max(1.0, std::fabs(theta[k]))) sel.push_back(k);
         if (sel.empty())
@@ -543,7 +552,7 @@ struct Solver {
             // every correction lies in the current space: the space is invariant
             // to working precision, so the Ritz pairs are converged if their
             // residuals are
-            return end((!mixed && maxr <= tol_r) ? ADC_OK : ADC_E_NOCONV);
+            return end((!stage && maxr <= tol_r) ? ADC_OK : ADC_E_NOCONV);
         }
         ADC_HIP(hipMemcpyAsync(d.V.p + (size_t)m * dim, d.D.p,
                                (size_t)kept * dim * sizeof(double), hipMemcpyDeviceToDevice,

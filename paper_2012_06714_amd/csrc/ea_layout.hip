@@ -69,6 +69,8 @@ template void ea_pairs<double, double>(Engine&, const double*, int, int, int, do
                                        double*, double*, double*);
 template void ea_pairs<float, bf16_t>(Engine&, const float*, int, int, int, bf16_t*, bf16_t*,
                                       bf16_t*, bf16_t*, float*);
+template void ea_pairs<float, float>(Engine&, const float*, int, int, int, float*, float*, float*,
+                                     float*, float*);
 
 // ---------------------------------------------------------------------------
 // resident operands
@@ -105,29 +107,33 @@ static void to_f32(adc_ctx* c, const DBuf<double>& src, DBuf<float>& dst) {
 }
 
 // bytes the arranged operands still to be made would take
-static size_t layout_bytes(const adc_ctx* c, bool mixed) {
+static size_t layout_bytes(const adc_ctx* c, int level) {
     const size_t O = c->O, V = c->V, Q = c->Q;
     const size_t big = O * O * V * V, g = O * O * O * V, bvo = c->Bvo.p ? 0 : O * V * Q;
     size_t b = 0;
     if (!c->eal.ready) b += 6 * big * 8 + g * 8 + bvo * 8;
-    if (mixed && !c->eal.ready_mixed) b += 7 * big * 2 + g * 4 + (c->fBvo.p ? 0 : O * V * Q * 4);
+    const size_t f32_small = (c->eal.fG.p ? 0 : g * 4) + (c->fBvo.p ? 0 : O * V * Q * 4);
+    if (level == 1 && !c->eal.ready_mixed) b += 7 * big * 2 + f32_small;
+    if (level == 2 && !c->eal.ready_f32) b += 6 * big * 4 + f32_small;
     return b;
 }
 
-bool ea_layout_use(adc_ctx* c, bool mixed) {
+bool ea_layout_use(adc_ctx* c, int level) {
     if (c->kind != ADC_EA || c->ea_layout == 0) return false;
     if (c->order == 2 || c->ea_layout == 1) return true;
-    if (c->eal.ready && (!mixed || c->eal.ready_mixed)) return true;
+    if (c->eal.ready && (level == 0 || (level == 1 && c->eal.ready_mixed) ||
+                         (level == 2 && c->eal.ready_f32)))
+        return true;
     // automatic: the operands still to be made must fit in half the free memory
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
         (void)hipGetLastError();
         return false;
     }
-    return layout_bytes(c, mixed) <= fr / 2;
+    return layout_bytes(c, level) <= fr / 2;
 }
 
-void ea_layout_build(adc_ctx* c, bool mixed) {
+void ea_layout_build(adc_ctx* c, int level) {
     if (c->kind != ADC_EA) return;
     Engine& E = c->E;
     const size_t O = c->O, V = c->V, Q = c->Q;
@@ -157,8 +163,20 @@ void ea_layout_build(adc_ctx* c, bool mixed) {
         permute<double>(E, 1.0, "jkla", c->ooov.p, 1.0, "ajkl", L.G.p);
         L.ready = true;
     }
-    if (mixed) {
+    if (level >= 1) {
         if (!c->fBvo.p) to_f32(c, c->Bvo, c->fBvo);
+        if (!L.fG.p) to_f32(c, L.G, L.fG);
+    }
+    if (level == 2 && !L.ready_f32) {
+        to_f32(c, L.ttT1, L.fttT1);
+        to_f32(c, L.ttT2, L.fttT2);
+        to_f32(c, L.tT1, L.ftT1);
+        to_f32(c, L.tD, L.ftD);
+        to_f32(c, L.oovvT, L.foovvT);
+        to_f32(c, L.tT, L.ftT);
+        L.ready_f32 = true;
+    }
+    if (level == 1) {
         if (!L.ready_mixed) {
             to_bf16(c, L.ttT1, L.httT1);
             to_bf16(c, L.ttT2, L.httT2);
@@ -167,7 +185,6 @@ void ea_layout_build(adc_ctx* c, bool mixed) {
             to_bf16(c, L.oovvT, L.hoovvT);
             to_bf16(c, L.tT, L.htT);
             to_bf16(c, c->ovov, L.hovov);
-            to_f32(c, L.G, L.fG);
             L.ready_mixed = true;
         }
     }

@@ -85,7 +85,7 @@ void gemm_map(Engine& E, bool ta, bool tb, long long M, long long N, long long K
 
 // The same for compute type T with the output in its accumulator type,
 // tagged with a profile kind (split-K keeps the tag).  Instantiated for
-// (TI, T) = (f64, f64), (bf16, bf16).
+// (TI, T) = (f64, f64), (bf16, bf16), (f32, f32).
 template <typename TI, typename T>
 void gemm_acc(Engine& E, bool ta, bool tb, long long M, long long N, long long K,
               typename AccOf<T>::type alpha, const TI* A, long long lda, const TI* B, long long ldb,

@@ -200,28 +200,37 @@ Views<float> views<float>(adc_ctx* c) {
                         c->ftt.p,   c->fgam.p,  c->fOm.p,   c->fPi.p};
 }
 
-// compute type of the particle-particle GEMMs: FP64, or BF16 in the mixed mode
-template <typename T> struct PPType { using type = double; };
-template <> struct PPType<float> { using type = bf16_t; };
+// Precision levels of sigma: FP64; FP32 storage with BF16 products (the big
+// operands of the arranged EA products and of the particle-particle term in
+// BF16); FP32 storage with FP32 products.  T is the storage of the vectors
+// and most operands, TB that of the large product operands.
 
-// Operands of the arranged EA path (ea_layout.hip): TB is the storage of the
-// large product operands (FP64, or BF16 in the mixed mode).
-template <typename T>
+// Operands of the arranged EA path (ea_layout.hip)
+template <typename T, typename TB>
 struct EaOps {
-    using TB = typename PPType<T>::type;
     const TB *ttT1, *ttT2, *tT1, *tD, *oovvT, *tT, *ovov;
     const T *G, *Bvo;
 };
 
-static EaOps<double> ea_ops(adc_ctx* c, double*) {
+static EaOps<double, double> ea_ops(adc_ctx* c, double*, double*) {
     auto& L = c->eal;
-    return EaOps<double>{L.ttT1.p, L.ttT2.p, L.tT1.p, L.tD.p, L.oovvT.p, L.tT.p, c->ovov.p,
-                         L.G.p, c->Bvo.p};
+    return {L.ttT1.p, L.ttT2.p, L.tT1.p, L.tD.p, L.oovvT.p, L.tT.p, c->ovov.p, L.G.p, c->Bvo.p};
 }
-static EaOps<float> ea_ops(adc_ctx* c, float*) {
+static EaOps<float, bf16_t> ea_ops(adc_ctx* c, float*, bf16_t*) {
     auto& L = c->eal;
-    return EaOps<float>{L.httT1.p, L.httT2.p, L.htT1.p, L.htD.p, L.hoovvT.p, L.htT.p, L.hovov.p,
-                        L.fG.p, c->fBvo.p};
+    return {L.httT1.p, L.httT2.p, L.htT1.p, L.htD.p, L.hoovvT.p, L.htT.p, L.hovov.p,
+            L.fG.p, c->fBvo.p};
+}
+static EaOps<float, float> ea_ops(adc_ctx* c, float*, float*) {
+    auto& L = c->eal;
+    return {L.fttT1.p, L.fttT2.p, L.ftT1.p, L.ftD.p, L.foovvT.p, L.ftT.p, c->fovov.p,
+            L.fG.p, c->fBvo.p};
+}
+
+// sigma precision level of a (T, TB) pair: 0 FP64, 1 BF16 products, 2 FP32 products
+template <typename T, typename TB>
+constexpr int level_of() {
+    return sizeof(T) == 8 ? 0 : sizeof(TB) == 2 ? 1 : 2;
 }
 
 static GemmOut omap(long long rsplit, long long rs1, long long rs2, long long csplit, long long cs1,
@@ -248,12 +257,10 @@ enum ArrSlot { A_P1 = 40, A_P2, A_D, A_PM, A_DW, A_W, A_X1, A_F2, A_W2, A_X, A_R
 //                   sum_Q (ac|Q) W_cQ),
 //   F2 = A~ + C~  is written as [z][k][b][d] for its (bd|Q) product,
 //   S2 gets every (z,a)x(i,b) and (i,a)x(z,b) product through an output map.
-template <typename T>
+template <typename T, typename TB>
 static void sigma_ea_arranged(adc_ctx* c, const T* Y1, const T* Y2, T* S1, T* S2, int nvec) {
-    using TB = typename PPType<T>::type;
     Engine& E = c->E;
-    const bool mixed = sizeof(T) == 4;
-    ea_layout_build(c, mixed);
+    ea_layout_build(c, level_of<T, TB>());
     const Views<T> v = views<T>(c);
     const long long Z = nvec, O = c->O, V = c->V, Q = c->Q;
     const long long OV = O * V, VV = V * V, OVV = O * VV;
@@ -284,7 +291,7 @@ static void sigma_ea_arranged(adc_ctx* c, const T* Y1, const T* Y2, T* S1, T* S2
 
     T* W = slot<T>(E, A_W, (size_t)(Z * V * Q));
     if (o3) {
-        const EaOps<T> a = ea_ops(c, (T*)nullptr);
+        const EaOps<T, TB> a = ea_ops(c, (T*)nullptr, (TB*)nullptr);
         // sigma_a += sum_jb (Y_baj - 2 Y_abj) Gamma_jb
         gemm_map<T, T>(E, false, true, Z * V, 1, OV, 1.0, Dw, OV, v.gam, OV, 1.0, S1,
                        GemmOut::rowmajor(1));
@@ -340,7 +347,7 @@ static void sigma_ea_arranged(adc_ctx* c, const T* Y1, const T* Y2, T* S1, T* S2
                    GemmOut::rowmajor(V));
 }
 
-template <typename T>
+template <typename T, typename TB>
 void sigma_block(adc_ctx* c, const double* X, double* Yout, int nvec) {
     Engine& E = c->E;
     E.ext.Z = nvec;
@@ -356,7 +363,7 @@ void sigma_block(adc_ctx* c, const double* X, double* Yout, int nvec) {
         bool old;
         Bf16Scope(Engine& en, bool on) : e(en), old(en.bf16) { e.bf16 = on; }
         ~Bf16Scope() { e.bf16 = old; }
-    } scope(E, sizeof(T) == 4);
+    } scope(E, level_of<T, TB>() == 1);
 
     T* Y1 = slot<T>(E, S_Y1, (size_t)nvec * n1);
     T* Y2 = slot<T>(E, S_Y2, (size_t)nvec * len2);
@@ -369,8 +376,8 @@ void sigma_block(adc_ctx* c, const double* X, double* Yout, int nvec) {
 
     const bool ea3 = c->order == 3 && c->kind == ADC_EA;
     const bool ip3 = c->order == 3 && c->kind == ADC_IP;
-    if (ea_layout_use(c, sizeof(T) == 4)) {
-        sigma_ea_arranged<T>(c, Y1, Y2, S1, S2, nvec);
+    if (ea_layout_use(c, level_of<T, TB>())) {
+        sigma_ea_arranged<T, TB>(c, Y1, Y2, S1, S2, nvec);
     } else {
         sigma_adc2_terms<T>(c, v, Y1, Y2, S1, S2, nvec);
         if (ea3) sigma_adc3_ea_terms<T>(c, v, Y1, Y2, S1, S2, nvec);
@@ -382,8 +389,10 @@ void sigma_block(adc_ctx* c, const double* X, double* Yout, int nvec) {
     copy_rows<T, double>(E, S1, n1, 0, Yout, dim, 0, nvec, n1, 0.0);
     double beta2 = 0.0;
     if (ea3) {
-        using P = typename PPType<T>::type;
-        const P* Bvv = sizeof(T) == 8 ? (const P*)c->Bvv.p : (const P*)c->hBvv.p;
+        using P = TB;
+        const P* Bvv = level_of<T, TB>() == 0   ? (const P*)c->Bvv.p
+                       : level_of<T, TB>() == 1 ? (const P*)c->hBvv.p
+                                                : (const P*)c->fBvv.p;
         P* Zp = slot<P>(E, S_T4, (size_t)nvec * len2);
         T* Zv = slot<T>(E, S_T1, (size_t)nvec * len2);
         copy_rows<double, P>(E, X, dim, n1, Zp, len2, 0, nvec, len2, 0.0);
@@ -409,9 +418,11 @@ void sigma_block(adc_ctx* c, const double* X, double* Yout, int nvec) {
 
 void sigma_eager(adc_ctx* c, const double* X, double* Y, int nvec, int precision) {
     if (precision == 1)
-        sigma_block<float>(c, X, Y, nvec);
+        sigma_block<float, bf16_t>(c, X, Y, nvec);
+    else if (precision == 2)
+        sigma_block<float, float>(c, X, Y, nvec);
     else
-        sigma_block<double>(c, X, Y, nvec);
+        sigma_block<double, double>(c, X, Y, nvec);
 }
 
 void drop_graphs(adc_ctx* c) {
@@ -545,7 +556,8 @@ void sigma_cost(const adc_ctx* c, int nvec, double* total, double* pp) {
     *pp = p;
 }
 
-template void sigma_block<double>(adc_ctx*, const double*, double*, int);
-template void sigma_block<float>(adc_ctx*, const double*, double*, int);
+template void sigma_block<double, double>(adc_ctx*, const double*, double*, int);
+template void sigma_block<float, bf16_t>(adc_ctx*, const double*, double*, int);
+template void sigma_block<float, float>(adc_ctx*, const double*, double*, int);
 
 }  // namespace adc

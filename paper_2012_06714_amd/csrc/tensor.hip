@@ -254,6 +254,9 @@ template void gemm_acc<double, double>(Engine&, bool, bool, long long, long long
 template void gemm_acc<bf16_t, bf16_t>(Engine&, bool, bool, long long, long long, long long, float,
                                        const bf16_t*, long long, const bf16_t*, long long, float,
                                        float*, GemmOut, int);
+template void gemm_acc<float, float>(Engine&, bool, bool, long long, long long, long long, float,
+                                     const float*, long long, const float*, long long, float,
+                                     float*, GemmOut, int);
 
 // compute type of an operand storage type: FP64 -> FP64, FP32 -> BF16 in the
 // mixed mode (FP32 otherwise), BF16 -> BF16

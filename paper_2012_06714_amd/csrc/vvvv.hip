@@ -83,5 +83,6 @@ void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx) {
 template void vvvv_apply<double, double>(adc_ctx*, const double*, const double*, double*,
                                          long long);
 template void vvvv_apply<bf16_t, float>(adc_ctx*, const bf16_t*, const bf16_t*, float*, long long);
+template void vvvv_apply<float, float>(adc_ctx*, const float*, const float*, float*, long long);
 
 }  // namespace adc

@@ -163,11 +163,15 @@ def test_ea_sigma_both_contraction_paths(order, layout):
     s64 = ctx.sigma(Xd).cpu().numpy()
     ctx.set_option("precision", 1)
     smx = ctx.sigma(Xd).cpu().numpy()
+    ctx.set_option("precision", 2)
+    s32 = ctx.sigma(Xd).cpu().numpy()
     ctx.close()
     s_ref = ref.sigma(X)
     assert np.abs(s64 - s_ref).max() <= 1e-11 * np.abs(s_ref).max()
     rel = np.linalg.norm(smx - s_ref, axis=1) / np.linalg.norm(s_ref, axis=1)
     assert 1e-9 < rel.max() < 1e-2, rel
+    rel32 = np.linalg.norm(s32 - s_ref, axis=1) / np.linalg.norm(s_ref, axis=1)
+    assert 1e-12 < rel32.max() < 1e-5, rel32
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -220,30 +224,37 @@ def test_mixed_sigma_close_to_fp64(kind, order):
     s64 = ctx.sigma(Xd).cpu().numpy()
     ctx.set_option("precision", 1)
     smx = ctx.sigma(Xd).cpu().numpy()
+    ctx.set_option("precision", 2)
+    s32 = ctx.sigma(Xd).cpu().numpy()
     ctx.close()
     s_ref = ref.sigma(X)
     assert np.abs(s64 - s_ref).max() <= 1e-11 * np.abs(s_ref).max()
     rel = np.linalg.norm(smx - s_ref, axis=1) / np.linalg.norm(s_ref, axis=1)
     assert rel.max() < 1e-2, rel
     assert rel.max() > 1e-9   # really ran in reduced precision
+    # FP32 products and sums: a few FP32 ulps (2^-23) times the square root of
+    # the summed length
+    rel32 = np.linalg.norm(s32 - s_ref, axis=1) / np.linalg.norm(s_ref, axis=1)
+    assert 1e-12 < rel32.max() < 1e-5, rel32
 
 
+@pytest.mark.parametrize("precision", [1, 2])
 @pytest.mark.parametrize("kind", ["ea", "ip"])
-def test_mixed_davidson_refines_to_fp64(kind):
-    """Mixed-precision Davidson with FP64 refinement reaches the dense FP64
-    eigenvalues (1e-8 Eh) and spectroscopic factors (1e-6 in units of
-    max(1, |P|))."""
+def test_mixed_davidson_refines_to_fp64(kind, precision):
+    """Mixed-precision Davidson (BF16 products, then FP64; or BF16, FP32, then
+    FP64) reaches the dense FP64 eigenvalues (1e-8 Eh) and spectroscopic
+    factors (1e-6 in units of max(1, |P|))."""
     from oracle.radc import RADC
     from synthetic import small_system
     O, V, Q, seed = 4, 24, 60, 6
     eps, B = small_system(O, V, Q, seed)
-    _say(f"case mixed davidson {kind}")
+    _say(f"case mixed davidson {kind} precision={precision}")
     ref = RADC(eps, B, O, 3, kind)
     w, v = np.linalg.eigh(ref.explicit())
     nroots = 4
     P_ref = ref.spec_factors(v[:, :nroots].T)
     ctx = _ctx(eps, B, O, 3, kind)
-    ctx.set_option("precision", 1)
+    ctx.set_option("precision", precision)
     ctx.set_option("tol_e", 1e-10)
     ctx.set_option("tol_r", 1e-6)
     e, P, _, it, conv = ctx.davidson(nroots, want_vectors=False)
