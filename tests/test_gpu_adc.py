@@ -291,3 +291,36 @@ def test_c2_sigma_sampled_against_oracle():
     assert np.abs(Y[0] - S[0]).max() <= 1e-11 * scale0
     scale1 = np.abs(S[1, n1:]).max()
     assert np.abs(Y[1, n1:] - S[1, n1:]).max() <= 1e-11 * scale1
+
+
+def test_c3_sigma_properties_at_full_size():
+    """EA-ADC(3), O=40, V=460, Naux=1400 (the larger workload, 32 trial vectors
+    per call in its solves): properties that hold at any size, on two vectors
+    of a 32-vector call.  M is symmetric in the Z basis, so x.(M y) = y.(M x);
+    sigma is linear; the BF16- and FP32-product levels stay within their
+    rounding bounds of the FP64 result.  (The oracle's sigma at this size
+    would take minutes of CPU time; element-by-element parity is checked at
+    O=20, V=180 and below.)"""
+    from synthetic import make_system, random_vectors
+    eps, B, wl = make_system("c3")
+    _say("case c3 sigma properties")
+    ctx = _ctx(eps, B, wl.nocc, wl.order, wl.kind)
+    del B
+    X = torch.tensor(random_vectors(ctx.dim, wl.block, 23), device="cuda")
+    X /= X.norm(dim=1, keepdim=True)
+    X[2] = 0.75 * X[0] - 1.5 * X[1]
+    Y = ctx.sigma(X)
+    x, y = X[0], X[1]
+    mx, my = Y[0], Y[1]
+    lhs, rhs = float(x @ my), float(y @ mx)
+    # both products are sums of dim terms of size |x||My|: FP64 rounding bound
+    assert abs(lhs - rhs) <= 1e-12 * float(my.norm()) * float(x.norm()) * (ctx.dim ** 0.5)
+    lin = Y[2] - (0.75 * Y[0] - 1.5 * Y[1])
+    assert float(lin.abs().max()) <= 1e-11 * float(Y[:2].abs().max())
+    for level, bound in ((1, 1e-2), (2, 1e-5)):
+        ctx.set_option("precision", level)
+        Yl = ctx.sigma(X)
+        rel = ((Yl[:2] - Y[:2]).norm(dim=1) / Y[:2].norm(dim=1)).max().item()
+        _say(f"level {level}: relative difference {rel:.3e}")
+        assert 1e-12 < rel < bound
+    ctx.close()
