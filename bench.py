@@ -168,6 +168,8 @@ def main():
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed", "mixed3"])
     ap.add_argument("--no-davidson", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="time sigma replayed from captured HIP graphs (same kernels)")
     ap.add_argument("--tune-log", action="store_true", help="log the GEMM autotuner's choices")
     ap.add_argument("--verbose", action="store_true", help="per-iteration solver lines on stderr")
     ap.add_argument("--calib-copy", action="store_true",
@@ -219,6 +221,10 @@ def main():
 
     def time_sigma(prec):
         ctx.set_option("precision", LEVEL[prec])
+        # with --graph the timed steps replay the call from a captured HIP graph
+        # (captured at the first call after an eager warm-up); the event-timed
+        # calls that split out the particle-particle term always run eagerly
+        ctx.set_option("graph", 1 if args.graph else 0)
         for _ in range(args.warmup):
             ctx.sigma(X, out=Y)
         torch.cuda.synchronize()
@@ -234,6 +240,7 @@ def main():
         return dt, float(np.mean(pp))
 
     def solve(prec, e_ref=None, tol_r=1e-7):
+        ctx.set_option("graph", 0)
         ctx.set_option("precision", LEVEL[prec])
         ctx.set_option("block", wl.block)
         ctx.set_option("tol_e", 1e-7)
