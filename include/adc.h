@@ -101,7 +101,7 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
  *                 particle-particle term (default 4096); a smaller slab means
  *                 more, smaller rebuild blocks
  *   "pp_blocks"   minimum number of blocks of a in that rebuild (default 0:
- *                 min(12, V/8) in FP64, 1 in the mixed mode); block k
+ *                 min(24, V/8) in FP64, 1 at the reduced-precision levels); block k
  *                 rebuilds only the pairs b >= its first a, so more blocks
  *                 mean fewer rebuilt flops but smaller products
  *   "workspace_limit"  bytes the context may allocate in total

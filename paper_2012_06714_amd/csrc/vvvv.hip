@@ -8,12 +8,12 @@
 // are rebuilt: one matrix-core GEMM over Q,
 //   rows (a, c) of B_vv (a in A)  x  rows (b, d) of B_vv (b >= a0),
 // whose epilogue scatters the result into the slab K[a][b][c][d].  The slab
-// then serves two contractions, both GEMMs contiguous in the summed pair:
-//   out[x][a][b] = sum_(cd) in[x][(c,d)]  K[a][b][(c,d)]          (b >= a0)
-//   out[x][b][a] = sum_(cd) inT[x][(c,d)] K[a][b][(c,d)]          (b >= a0)
-// where inT[x][c][d] = in[x][d][c]; pairs with b < a0 were produced as mirrors
-// by earlier blocks, and pairs with both a and b in the block are written by
-// both products (the same value).  The rebuild of a block costs 2 Naux na V^2 (V - a0)
+// then serves the direct and the mirrored pairs in one GEMM, contiguous in the
+// summed pair, over the stacked inputs [in; inT] (inT[x][c][d] = in[x][d][c]):
+//   D[x][a][b] = sum_(cd) in[x][(c,d)]  K[a][b][(c,d)]          (b >= a0)
+//   T[x][a][b] = sum_(cd) inT[x][(c,d)] K[a][b][(c,d)] = out[x][b][a]
+// and out takes D where b lies at or past the first a of a's block, else the
+// mirror T[x][b][a] written by the earlier block of b.  The rebuild of a block costs 2 Naux na V^2 (V - a0)
 // flops, Naux V^3 (V + na) over all blocks of size na instead of 2 Naux V^4;
 // the contraction 2 nx V^4 as before.
 #include "context.hpp"
@@ -21,6 +21,34 @@
 #include <algorithm>
 
 namespace adc {
+
+// out[x][p][q] from the two halves of the per-block products: D[x][p][q]
+// (direct) where q lies at or past the first a of p's block, else the
+// mirror T[x][q][p] (written when q's block was processed, as p >= q's first
+// a).  32x32 tiles of (p, q); the mirror tile is read transposed through LDS.
+template <typename TO>
+__global__ void k_pp_assemble(const TO* __restrict__ D, const TO* __restrict__ T,
+                              TO* __restrict__ out, int V, int ta, int nt) {
+    __shared__ TO tile[32][33];
+    const int p0 = (blockIdx.x / nt) * 32, q0 = (blockIdx.x % nt) * 32;
+    const long long x = blockIdx.y;
+    const long long VV = (long long)V * V;
+    const TO* Dx = D + x * VV;
+    const TO* Tx = T + x * VV;
+    TO* ox = out + x * VV;
+    const int tx = threadIdx.x, ty = threadIdx.y;   // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const int q = q0 + r, p = p0 + tx;
+        tile[r][tx] = (q < V && p < V) ? Tx[(long long)q * V + p] : TO(0);   // T[q][p]
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int p = p0 + r, q = q0 + tx;
+        if (p >= V || q >= V) continue;
+        const long long o = (long long)p * V + q;
+        ox[o] = (q >= (p / ta) * ta) ? Dx[o] : tile[tx][r];
+    }
+}
 
 template <typename T, typename TO>
 void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx) {
@@ -31,17 +59,28 @@ void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx) {
     ta_max = std::min(ta_max, V);
     // more blocks rebuild fewer mirrored pairs (Naux V^3 (V + na) flops) but
     // make smaller products: at least pp_blocks of them (default: FP64, whose
-    // products run near the matrix-core peak at any size, 12 blocks of at
+    // products run near the matrix-core peak at any size, 24 blocks of at
     // least 8 values of a; BF16, whose short-K rebuild is bound by its
     // stores, as few as the slab allows)
     const long long want = c->pp_blocks > 0 ? c->pp_blocks
-                           : sizeof(T) == 8 ? std::min<long long>(12, V / 8)
+                           : sizeof(T) == 8 ? std::min<long long>(24, V / 8)
                                             : 1;
     const long long nblk = std::min(V, std::max((V + ta_max - 1) / ta_max, want));
     const long long ta = (V + nblk - 1) / nblk;            // balanced a-blocks
     T* K = (T*)E.scratch.get(30, sizeof(T) * ta * V3);
-    T* inT = nblk > 1 ? (T*)E.scratch.get(29, sizeof(T) * nx * VV) : nullptr;
-    if (inT) pair_transform<T, T>(E, in, nx * VV, 0, inT, nx * VV, 0, 1, nx, (int)V, 0.0, 1.0, 0.0);
+    // several blocks: the inputs stacked as [in; inT] (inT[x][c][d] = in[x][d][c])
+    // so that one product per block serves the direct and the mirrored pairs,
+    // reading the slab once; its results D (rows 0..nx-1) and T (rows nx..)
+    // are assembled into out at the end
+    T* AB = nullptr;
+    TO* DT = nullptr;
+    if (nblk > 1) {
+        AB = (T*)E.scratch.get(29, sizeof(T) * 2 * nx * VV);
+        ADC_HIP(hipMemcpyAsync(AB, in, sizeof(T) * nx * VV, hipMemcpyDeviceToDevice, E.stream));
+        pair_transform<T, T>(E, in, nx * VV, 0, AB + nx * VV, nx * VV, 0, 1, nx, (int)V, 0.0, 1.0,
+                             0.0);
+        DT = (TO*)E.scratch.get(27, sizeof(TO) * 2 * nx * VV);
+    }
     using A = typename AccOf<T>::type;
     for (long long a0 = 0; a0 < V; a0 += ta) {
         const long long na = std::min(ta, V - a0), nb = V - a0;
@@ -55,28 +94,25 @@ void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx) {
         const T* Ba = Bvv + a0 * V * Q;
         gemm_run<T, T, T>(E, false, true, na * V, nb * V, Q, A(1), Ba, Q, 0, Ba, Q, 0, A(0),
                            K, slab, 1, 1);
-        GemmOut direct;                                    // x x (a, b-a0) -> out[x][a][b]
-        direct.rs2 = VV;
-        direct.csplit = nb;
-        direct.cs1 = V;
-        direct.cs2 = 1;
-        gemm_acc<T, T>(E, false, true, nx, na * nb, VV, A(1), in, VV, K, VV, A(0),
-                       out + a0 * V + a0, direct, 2);
-        E.gemm_flops += 2LL * na * V * nb * V * Q + 2LL * nx * na * nb * VV;
-        if (nb > na) {
-            // mirrors out[x][b][a] = sum_(cd) inT[x][(c,d)] K[a][b][(c,d)] as one product
-            // over all columns (a, b >= a0): the pairs with b inside the block repeat
-            // direct results of the same value, which costs na/nb of the product but
-            // keeps every operand row contiguous
-            GemmOut mirror;                                // x x (a, b-a0) -> out[x][b][a]
-            mirror.rs2 = VV;
-            mirror.csplit = nb;
-            mirror.cs1 = 1;
-            mirror.cs2 = V;
-            gemm_acc<T, T>(E, false, true, nx, na * nb, VV, A(1), inT, VV, K, VV, A(0),
-                           out + a0 * V + a0, mirror, 2);
-            E.gemm_flops += 2LL * nx * na * nb * VV;
-        }
+        GemmOut pairs;                                     // x x (a, b-a0) -> [x][a][b]
+        pairs.rs2 = VV;
+        pairs.csplit = nb;
+        pairs.cs1 = V;
+        pairs.cs2 = 1;
+        if (nblk > 1)
+            gemm_acc<T, T>(E, false, true, 2 * nx, na * nb, VV, A(1), AB, VV, K, VV, A(0),
+                           DT + a0 * V + a0, pairs, 2);
+        else
+            gemm_acc<T, T>(E, false, true, nx, na * nb, VV, A(1), in, VV, K, VV, A(0),
+                           out + a0 * V + a0, pairs, 2);
+        E.gemm_flops += 2LL * na * V * nb * V * Q + 2LL * (nblk > 1 ? 2 : 1) * nx * na * nb * VV;
+    }
+    if (nblk > 1) {
+        const int nt = (int)((V + 31) / 32);
+        ADC_REQUIRE(nx <= 65535, "particle-particle term: too many rows");
+        hipLaunchKernelGGL(k_pp_assemble<TO>, dim3((unsigned)(nt * nt), (unsigned)nx),
+                           dim3(32, 8), 0, E.stream, DT, DT + nx * VV, out, (int)V, (int)ta, nt);
+        ADC_HIP(hipGetLastError());
     }
 }
 
