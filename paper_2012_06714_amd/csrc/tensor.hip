@@ -171,19 +171,28 @@ ADC_RUN_INST(float, float, bf16_t)
 template <typename A>
 __global__ void k_splitk_reduce(const A* __restrict__ part, int S, long long batch, long long M,
                                 long long N, A* __restrict__ C, GemmOut o, A beta) {
+    // block: 64 consecutive outputs (one per lane, coalesced) x G chunk groups
+    // (blockDim.y); group g sums chunks g, g+G, ..., then group 0 adds the G
+    // partial sums in order: a fixed summation order for every launch
+    __shared__ A red[16][64];
     const long long MN = M * N, tot = batch * MN;
+    const int lane = threadIdx.x, g = threadIdx.y, G = blockDim.y;
+    const long long e = (long long)blockIdx.x * 64 + lane;
+    A v = 0;
+    if (e < tot)
+        for (int s = g; s < S; s += G) v += part[(long long)s * tot + e];
+    red[g][lane] = v;
+    __syncthreads();
+    if (g != 0 || e >= tot) return;
+    A sum = 0;
+    for (int k = 0; k < G; ++k) sum += red[k][lane];
     const long long rsplit = o.rsplit > 0 ? o.rsplit : M, csplit = o.csplit > 0 ? o.csplit : N;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
-         e += (long long)gridDim.x * blockDim.x) {
-        A v = 0;
-        for (int s = 0; s < S; ++s) v += part[s * tot + e];
-        const long long b = e / MN, r = e - b * MN;
-        const long long m = r / N, n = r - m * N;
-        const long long m1 = m / rsplit, n1 = n / csplit;
-        A* dst = C + b * o.sC + m1 * o.rs1 + (m - m1 * rsplit) * o.rs2 + n1 * o.cs1 +
-                 (n - n1 * csplit) * o.cs2;
-        *dst = (beta == A(0)) ? v : beta * *dst + v;
-    }
+    const long long b = e / MN, r = e - b * MN;
+    const long long m = r / N, n = r - m * N;
+    const long long m1 = m / rsplit, n1 = n / csplit;
+    A* dst = C + b * o.sC + m1 * o.rs1 + (m - m1 * rsplit) * o.rs2 + n1 * o.cs1 +
+             (n - n1 * csplit) * o.cs2;
+    *dst = (beta == A(0)) ? sum : beta * *dst + sum;
 }
 
 // number of k-chunks for a product of `wgs` 64x64 workgroups: enough chunks
@@ -231,10 +240,11 @@ static void gemm_any(Engine& E, bool ta, bool tb, long long M, long long N, long
         gemm_run<TI, T, Acc>(E, ta, tb, M, N, Klast, alpha, A + (S - 1) * offA, lda, sA,
                              B + (S - 1) * offB, ldb, sB, Acc(0), part + (S - 1) * MNB,
                              GemmOut::rowmajor(N, M * N), batch, kind);
-        long long g = (MNB + 255) / 256;
-        if (g > 4096) g = 4096;
-        hipLaunchKernelGGL(k_splitk_reduce<Acc>, dim3((unsigned)g), dim3(256), 0, E.stream, part,
-                           (int)S, batch, M, N, C, out, beta);
+        const long long nb = (MNB + 63) / 64;
+        ADC_REQUIRE(nb < (1LL << 31), "split-K: too many outputs");
+        const int G = (int)std::min<long long>(16, S);
+        hipLaunchKernelGGL(k_splitk_reduce<Acc>, dim3((unsigned)nb), dim3(64, G), 0, E.stream,
+                           part, (int)S, batch, M, N, C, out, beta);
         ADC_HIP(hipGetLastError());
         return;
     }
