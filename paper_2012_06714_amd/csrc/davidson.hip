@@ -147,8 +147,9 @@ struct Dav {
         ADC_HIP(hipStreamSynchronize(E.stream));
     }
 
-    // orthonormalise nd rows of Dm against V[0:m] and among themselves.  Two
-    // passes of: block classical Gram-Schmidt against V (one long-K GEMM each
+    // orthonormalise nd rows of Dm against V[0:m] and among themselves.  One
+    // pass, or two when the first shrank a direction below 1e-3 of its norm,
+    // of: block classical Gram-Schmidt against V, twice (one long-K GEMM each
     // way), then the block's own Gram matrix G = Dm Dm^T, diagonalised on the
     // host (nd is small), and Dm <- L^-1/2 U^T Dm over the eigenpairs with
     // lambda > max(1e-20, 1e-14 lambda_max): directions that fall below (rows
@@ -166,7 +167,8 @@ struct Dav {
         ADC_HIP(hipGetLastError());
         tmp.ensure((size_t)nd * dim, &c->arena);
         std::vector<double> G, T;
-        for (int pass = 0; pass < 2 && nd > 0; ++pass) {
+        bool last = false;
+        for (int pass = 0; pass < 2 && nd > 0 && !last; ++pass) {
             if (m > 0) {
                 for (int cgs = 0; cgs < 2; ++cgs) {
                     gemm_rm<double>(E, false, true, nd, m, dim, 1.0, Dm, dim, 0, V.p, dim, 0, 0.0,
@@ -193,13 +195,20 @@ struct Dav {
             const double cut = std::max(1e-20, 1e-14 * lmax);
             T.clear();
             int kept = 0;
+            double lmin_kept = INFINITY;
             for (int k = 0; k < nd; ++k) {
                 if (!(lam[k] > cut) || !std::isfinite(lam[k])) continue;
                 const double f = 1.0 / std::sqrt(lam[k]);
                 for (int j = 0; j < nd; ++j) T.push_back(U[(size_t)j * nd + k] * f);
                 ++kept;
+                lmin_kept = std::min(lmin_kept, lam[k]);
             }
             if (kept == 0) return 0;
+            // the second pass only when the first left directions of small
+            // norm (unit rows shrunk below 1e-3 by the projections or among
+            // themselves): scaling them back up by 1/sqrt(lambda) would also
+            // scale their remaining components along V
+            if (pass == 0 && lmin_kept >= 1e-6) last = true;
             ADC_HIP(hipMemcpyAsync(cmat.p, T.data(), T.size() * sizeof(double),
                                    hipMemcpyHostToDevice, E.stream));
             gemm_rm<double>(E, false, false, kept, dim, nd, 1.0, cmat.p, nd, 0, Dm, dim, 0, 0.0,
