@@ -98,12 +98,15 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
  *   "verbose"     1: per-iteration line on stderr; 2: also the solver's
  *                 wall time per phase (synchronising after each phase)
  *   "pp_slab_mb"  size bound in MiB of the rebuilt four-virtual slab of the
- *                 particle-particle term (default 4096); a smaller slab means
+ *                 particle-particle term (default 16384); a smaller slab means
  *                 more, smaller rebuild blocks
  *   "pp_blocks"   minimum number of blocks of a in that rebuild (default 0:
- *                 min(24, V/8) in FP64, 1 at the reduced-precision levels); block k
+ *                 min(24, V/8) in FP64, min(12, V/8) at the reduced-precision
+ *                 levels); block k
  *                 rebuilds only the pairs b >= its first a, so more blocks
  *                 mean fewer rebuilt flops but smaller products
+ *   "pp_group"    blocks of that rebuild contracted together in one product
+ *                 (default 0: 8, bounded by the slab size)
  *   "workspace_limit"  bytes the context may allocate in total
  *   "graph"       1 = replay sigma from HIP graphs captured per (vector
  *                 count, precision) after an eager warm-up call (default 0)

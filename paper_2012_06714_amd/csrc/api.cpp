@@ -136,6 +136,11 @@ int adc_set_option(adc_ctx* c, const char* key, double value) {
             return fail(c, ADC_E_ARG, "pp_blocks: a count >= 0");
         c->pp_blocks = (int)value;
         adc::drop_graphs(c);
+    } else if (k == "pp_group") {
+        if (value < 0 || value > 1e6 || value != std::floor(value))
+            return fail(c, ADC_E_ARG, "pp_group: a count >= 0");
+        c->pp_group = (int)value;
+        adc::drop_graphs(c);
     } else if (k == "ea_layout") {
         // EA sigma: -1 arranged operands when they fit in memory, 0 generic
         // contractions, 1 arranged operands

@@ -67,8 +67,9 @@ struct adc_ctx {
         adc::DBuf<float> fttT1, fttT2, ftT1, ftD, foovvT, ftT;
         bool ready = false, ready_mixed = false, ready_f32 = false;
     } eal;
-    long long pp_slab_bytes = 4LL << 30;   // rebuilt four-index slab (particle-particle term)
+    long long pp_slab_bytes = 16LL << 30;  // rebuilt four-index slab (particle-particle term)
     int pp_blocks = 0;                     // minimum number of a-blocks of that term (0: automatic)
+    int pp_group = 0;                      // blocks per contraction product (0: automatic)
 
     // sigma replayed from captured HIP graphs (sigma.hip)
     struct SigmaGraph {

@@ -58,18 +58,24 @@ void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx) {
     long long ta_max = std::max<long long>(1, c->pp_slab_bytes / (long long)(sizeof(T) * V3));
     ta_max = std::min(ta_max, V);
     // more blocks rebuild fewer mirrored pairs (Naux V^3 (V + na) flops) but
-    // make smaller products: at least pp_blocks of them (default: FP64, whose
-    // products run near the matrix-core peak at any size, 24 blocks of at
-    // least 8 values of a; BF16, whose short-K rebuild is bound by its
-    // stores, as few as the slab allows)
+    // make smaller rebuild products: at least pp_blocks of them (default 24
+    // blocks of at least 8 values of a in FP64, whose products run near the
+    // matrix-core peak at any size; 12 at the reduced levels, whose short-K
+    // rebuild is bound by its stores)
     const long long want = c->pp_blocks > 0 ? c->pp_blocks
-                           : sizeof(T) == 8 ? std::min<long long>(24, V / 8)
-                                            : 1;
+                                            : std::min<long long>(sizeof(T) == 8 ? 24 : 12, V / 8);
     const long long nblk = std::min(V, std::max((V + ta_max - 1) / ta_max, want));
     const long long ta = (V + nblk - 1) / nblk;            // balanced a-blocks
-    T* K = (T*)E.scratch.get(30, sizeof(T) * ta * V3);
+    // the contraction runs per group of up to pp_group consecutive blocks
+    // (default 8) sharing one slab [a - s0][b - s0][c][d] (b >= s0): larger
+    // products, at the price of the pairs b in [s0, a0) of the group's later
+    // blocks, which are never rebuilt and whose results are never used
+    const long long grp = std::max<long long>(
+        1, std::min<long long>(c->pp_group > 0 ? c->pp_group : 8, ta_max / ta));
+    const long long ts = std::min(V, grp * ta);
+    T* K = (T*)E.scratch.get(30, sizeof(T) * ts * V3);
     // several blocks: the inputs stacked as [in; inT] (inT[x][c][d] = in[x][d][c])
-    // so that one product per block serves the direct and the mirrored pairs,
+    // so that one product per group serves the direct and the mirrored pairs,
     // reading the slab once; its results D (rows 0..nx-1) and T (rows nx..)
     // are assembled into out at the end
     T* AB = nullptr;
@@ -82,30 +88,34 @@ void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx) {
         DT = (TO*)E.scratch.get(27, sizeof(TO) * 2 * nx * VV);
     }
     using A = typename AccOf<T>::type;
-    for (long long a0 = 0; a0 < V; a0 += ta) {
-        const long long na = std::min(ta, V - a0), nb = V - a0;
-        GemmOut slab;                                      // (a, c) x (b, d) -> [a][b-a0][c][d]
-        slab.rsplit = V;
-        slab.rs1 = nb * VV;
-        slab.rs2 = V;
-        slab.csplit = V;
-        slab.cs1 = VV;
-        slab.cs2 = 1;
-        const T* Ba = Bvv + a0 * V * Q;
-        gemm_run<T, T, T>(E, false, true, na * V, nb * V, Q, A(1), Ba, Q, 0, Ba, Q, 0, A(0),
-                           K, slab, 1, 1);
-        GemmOut pairs;                                     // x x (a, b-a0) -> [x][a][b]
+    for (long long s0 = 0; s0 < V; s0 += ts) {
+        const long long ns = std::min(ts, V - s0), nbs = V - s0;
+        for (long long a0 = s0; a0 < s0 + ns; a0 += ta) {
+            const long long na = std::min(ta, s0 + ns - a0), nb = V - a0;
+            GemmOut slab;                                  // (a, c) x (b, d) -> [a][b-s0][c][d]
+            slab.rsplit = V;
+            slab.rs1 = nbs * VV;
+            slab.rs2 = V;
+            slab.csplit = V;
+            slab.cs1 = VV;
+            slab.cs2 = 1;
+            const T* Ba = Bvv + a0 * V * Q;
+            gemm_run<T, T, T>(E, false, true, na * V, nb * V, Q, A(1), Ba, Q, 0, Ba, Q, 0, A(0),
+                               K + ((a0 - s0) * nbs + (a0 - s0)) * VV, slab, 1, 1);
+            E.gemm_flops += 2LL * na * V * nb * V * Q;
+        }
+        GemmOut pairs;                                     // x x (a, b-s0) -> [x][a][b]
         pairs.rs2 = VV;
-        pairs.csplit = nb;
+        pairs.csplit = nbs;
         pairs.cs1 = V;
         pairs.cs2 = 1;
         if (nblk > 1)
-            gemm_acc<T, T>(E, false, true, 2 * nx, na * nb, VV, A(1), AB, VV, K, VV, A(0),
-                           DT + a0 * V + a0, pairs, 2);
+            gemm_acc<T, T>(E, false, true, 2 * nx, ns * nbs, VV, A(1), AB, VV, K, VV, A(0),
+                           DT + s0 * V + s0, pairs, 2);
         else
-            gemm_acc<T, T>(E, false, true, nx, na * nb, VV, A(1), in, VV, K, VV, A(0),
-                           out + a0 * V + a0, pairs, 2);
-        E.gemm_flops += 2LL * na * V * nb * V * Q + 2LL * (nblk > 1 ? 2 : 1) * nx * na * nb * VV;
+            gemm_acc<T, T>(E, false, true, nx, ns * nbs, VV, A(1), in, VV, K, VV, A(0),
+                           out + s0 * V + s0, pairs, 2);
+        E.gemm_flops += 2LL * (nblk > 1 ? 2 : 1) * nx * ns * nbs * VV;
     }
     if (nblk > 1) {
         const int nt = (int)((V + 31) / 32);
