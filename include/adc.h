@@ -202,6 +202,13 @@ void adc_destroy(adc_ctx* ctx);
 int adc_last_stats(const adc_ctx* ctx, int* iters, long long* sigma_vectors,
                    int* mixed_iters, double* seconds);
 
+/* Device memory of the context (not in the paper: planning aid for large
+ * systems): bytes it holds now and the most it has held at once since
+ * adc_setup began (amplitudes, integrals, operand copies, Davidson space,
+ * scratch).  used, peak: host pointers, either may be NULL.  ADC_E_ARG for a
+ * NULL context. */
+int adc_workspace(const adc_ctx* ctx, long long* used, long long* peak);
+
 /* Several systems solved together (not in the paper: batching of its step 4
  * over independent systems).  ctxs: nsys distinct contexts, each set up and
  * configured as for adc_davidson.  flags:

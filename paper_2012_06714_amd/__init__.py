@@ -20,7 +20,7 @@ ADC_OK, ADC_E_ARG, ADC_E_OOM, ADC_E_HIP, ADC_E_STATE, ADC_E_NUMERIC, ADC_E_NOCON
 # every symbol declared in include/adc.h
 ABI_SYMBOLS = ("adc_setup", "adc_set_option", "adc_set_stream", "adc_dim", "adc_diag",
                "adc_sigma", "adc_davidson", "adc_spec_factors", "adc_set_guess",
-               "adc_last_error", "adc_destroy", "adc_last_stats", "adc_sigma_flops",
+               "adc_last_error", "adc_destroy", "adc_last_stats", "adc_workspace", "adc_sigma_flops",
                "adc_sigma_timed", "adc_history", "adc_mlp_nparams", "adc_precond_mlp",
                "adc_mlp_status", "adc_mlp_pairs", "adc_mlp_forward", "adc_mlp_loss_grad",
                "adc_mlp_adam", "adc_record_count", "adc_record_get", "adc_graph_launches",
@@ -51,6 +51,7 @@ def _load():
         "adc_last_error": (ctypes.c_char_p, [vp]),
         "adc_destroy": (None, [vp]),
         "adc_last_stats": (i, [vp, vp, vp, vp, vp]),
+        "adc_workspace": (i, [vp, vp, vp]),
         "adc_sigma_flops": (i, [vp, i, vp, vp]),
         "adc_sigma_timed": (i, [vp, vp, vp, i, vp, vp]),
         "adc_history": (i, [vp, i, vp, vp, vp, vp]),
@@ -229,6 +230,12 @@ class Context:
                                   ctypes.byref(sec)), self._h)
         return {"iters": it.value, "sigma_vectors": sv.value, "mixed_iters": mi.value,
                 "seconds": sec.value}
+
+    def workspace(self):
+        """Device bytes the context holds now and at most so far."""
+        used, peak = ctypes.c_longlong(), ctypes.c_longlong()
+        _check(lib.adc_workspace(self._h, ctypes.byref(used), ctypes.byref(peak)), self._h)
+        return {"used": used.value, "peak": peak.value}
 
     def graph_launches(self):
         return int(lib.adc_graph_launches(self._h))

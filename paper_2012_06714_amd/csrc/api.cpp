@@ -467,6 +467,13 @@ int adc_last_stats(const adc_ctx* c, int* iters, long long* sigvec, int* mixed_i
     return ADC_OK;
 }
 
+int adc_workspace(const adc_ctx* c, long long* used, long long* peak) {
+    if (!c) return fail(nullptr, ADC_E_ARG, "adc_workspace: NULL context");
+    if (used) *used = (long long)c->arena.used;
+    if (peak) *peak = (long long)c->arena.peak;
+    return ADC_OK;
+}
+
 void adc_destroy(adc_ctx* c) {
     if (!c) return;
     if (c->E.stream) (void)hipStreamSynchronize(c->E.stream);

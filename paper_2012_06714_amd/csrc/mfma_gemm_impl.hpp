@@ -447,7 +447,7 @@ static void launch_tiles(hipStream_t st, bool ta, bool tb, const TI* A, const TI
                          const GemmShape& g, long long batch, typename Mfma<T>::acc_t alpha,
                          typename Mfma<T>::acc_t beta) {
     const long long ntm = (g.M + BM - 1) / BM, ntn = (g.N + BN - 1) / BN;
-    ADC_REQUIRE(ntm * ntn < (1LL << 31), "gemm: grid too large");
+    ADC_REQUIRE(ntm * ntn * 64 * WGM * WGN < (1LL << 32), "gemm: grid too large");
     constexpr int NT = 64 * WGM * WGN;
     // the batch index runs over grid z (at most 65535 per launch)
     for (long long z0 = 0; z0 < batch; z0 += 65535) {
