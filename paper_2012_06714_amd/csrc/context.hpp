@@ -57,12 +57,13 @@ struct adc_ctx {
         // FP64: ttT1[k][d][j][c] = t~_jk^cd, ttT2[k][d][j][c] = t~_jk^dc,
         // tT1[k][d][j][c] = t_jk^cd, tD[i][a][k][d] = t_ik^da,
         // oovvT[i][b][j][c] = (ji|bc), tT[a][b][k][l] = t_kl^ab,
-        // G[a][j][k][l] = (jk|la) - 2 (jl|ka)
-        adc::DBuf<double> ttT1, ttT2, tT1, tD, oovvT, tT, G;
+        // G[a][j][k][l] = (jk|la) - 2 (jl|ka);
+        // H[i][b][Q] = sum_kd t~_ik^bd B^Q_kd and BH = B_ov + H (folded coupling operands)
+        adc::DBuf<double> ttT1, ttT2, tT1, tD, oovvT, tT, G, H, BH;
         // mixed: BF16 copies of the product operands (rounded through FP32,
         // as the FP32 copies are when staged) and FP32 G
         adc::DBuf<adc::bf16_t> httT1, httT2, htT1, htD, hoovvT, htT, hovov;
-        adc::DBuf<float> fG;
+        adc::DBuf<float> fG, fH, fBH;
         // FP32 copies for the FP32-product level
         adc::DBuf<float> fttT1, fttT2, ftT1, ftD, foovvT, ftT;
         bool ready = false, ready_mixed = false, ready_f32 = false;

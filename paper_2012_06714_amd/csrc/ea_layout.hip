@@ -111,8 +111,9 @@ static size_t layout_bytes(const adc_ctx* c, int level) {
     const size_t O = c->O, V = c->V, Q = c->Q;
     const size_t big = O * O * V * V, g = O * O * O * V, bvo = c->Bvo.p ? 0 : O * V * Q;
     size_t b = 0;
-    if (!c->eal.ready) b += 6 * big * 8 + g * 8 + bvo * 8;
-    const size_t f32_small = (c->eal.fG.p ? 0 : g * 4) + (c->fBvo.p ? 0 : O * V * Q * 4);
+    if (!c->eal.ready) b += 6 * big * 8 + g * 8 + bvo * 8 + 2 * O * V * Q * 8;
+    const size_t f32_small = (c->eal.fG.p ? 0 : g * 4) + (c->fBvo.p ? 0 : O * V * Q * 4) +
+                             (c->eal.fH.p ? 0 : 2 * O * V * Q * 4);
     if (level == 1 && !c->eal.ready_mixed) b += 7 * big * 2 + f32_small;
     if (level == 2 && !c->eal.ready_f32) b += 6 * big * 4 + f32_small;
     return b;
@@ -161,11 +162,22 @@ void ea_layout_build(adc_ctx* c, int level) {
         L.G.alloc(O * O * O * V, &c->arena);
         permute<double>(E, -2.0, "jlka", c->ooov.p, 0.0, "ajkl", L.G.p);
         permute<double>(E, 1.0, "jkla", c->ooov.p, 1.0, "ajkl", L.G.p);
+        // t~ is symmetric under the exchange of its (occupied, virtual) pairs, so
+        // H = t~ B_ov serves both sides: sum_kd t~_ik^bd (kd|Q) and sum_kd t~_ki^db (kd|Q)
+        L.H.alloc(O * V * Q, &c->arena);
+        gemm_map<double, double>(E, false, false, O * V, Q, O * V, 1.0, L.ttT1.p, O * V, c->Bov.p,
+                                 Q, 0.0, L.H.p, GemmOut::rowmajor(Q));
+        L.BH.alloc(O * V * Q, &c->arena);
+        ADC_HIP(hipMemcpyAsync(L.BH.p, c->Bov.p, O * V * Q * sizeof(double),
+                               hipMemcpyDeviceToDevice, E.stream));
+        axpy<double>(E, 1.0, L.H.p, L.BH.p, O * V * Q);
         L.ready = true;
     }
     if (level >= 1) {
         if (!c->fBvo.p) to_f32(c, c->Bvo, c->fBvo);
         if (!L.fG.p) to_f32(c, L.G, L.fG);
+        if (!L.fH.p) to_f32(c, L.H, L.fH);
+        if (!L.fBH.p) to_f32(c, L.BH, L.fBH);
     }
     if (level == 2 && !L.ready_f32) {
         to_f32(c, L.ttT1, L.fttT1);

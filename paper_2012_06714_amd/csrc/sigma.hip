@@ -205,26 +205,28 @@ Views<float> views<float>(adc_ctx* c) {
 // BF16); FP32 storage with FP32 products.  T is the storage of the vectors
 // and most operands, TB that of the large product operands.
 
-// Operands of the arranged EA path (ea_layout.hip)
+// Operands of the arranged EA path (ea_layout.hip); H = t~ B_ov and BH = B_ov + H
+// fold two of the t~ products into products over Naux
 template <typename T, typename TB>
 struct EaOps {
     const TB *ttT1, *ttT2, *tT1, *tD, *oovvT, *tT, *ovov;
-    const T *G, *Bvo;
+    const T *G, *Bvo, *H, *BH;
 };
 
 static EaOps<double, double> ea_ops(adc_ctx* c, double*, double*) {
     auto& L = c->eal;
-    return {L.ttT1.p, L.ttT2.p, L.tT1.p, L.tD.p, L.oovvT.p, L.tT.p, c->ovov.p, L.G.p, c->Bvo.p};
+    return {L.ttT1.p, L.ttT2.p, L.tT1.p, L.tD.p, L.oovvT.p, L.tT.p, c->ovov.p,
+            L.G.p,    c->Bvo.p, L.H.p,   L.BH.p};
 }
 static EaOps<float, bf16_t> ea_ops(adc_ctx* c, float*, bf16_t*) {
     auto& L = c->eal;
     return {L.httT1.p, L.httT2.p, L.htT1.p, L.htD.p, L.hoovvT.p, L.htT.p, L.hovov.p,
-            L.fG.p, c->fBvo.p};
+            L.fG.p,    c->fBvo.p, L.fH.p,   L.fBH.p};
 }
 static EaOps<float, float> ea_ops(adc_ctx* c, float*, float*) {
     auto& L = c->eal;
     return {L.fttT1.p, L.fttT2.p, L.ftT1.p, L.ftD.p, L.foovvT.p, L.ftT.p, c->fovov.p,
-            L.fG.p, c->fBvo.p};
+            L.fG.p,    c->fBvo.p, L.fH.p,   L.fBH.p};
 }
 
 // sigma precision level of a (T, TB) pair: 0 FP64, 1 BF16 products, 2 FP32 products
@@ -245,16 +247,19 @@ static GemmOut omap(long long rsplit, long long rs1, long long rs2, long long cs
     return o;
 }
 
-enum ArrSlot { A_P1 = 40, A_P2, A_D, A_PM, A_DW, A_W, A_X1, A_F2, A_W2, A_X, A_R, A_RP, A_WK };
+enum ArrSlot { A_P1 = 40, A_P2, A_PM = 43, A_DW, A_W, A_X1, A_F2, A_W2, A_X, A_RP = 51, A_WK };
 
 // EA sigma (ADC(2) terms and, for ADC(3), the second-order coupling and the
 // first-order 2p1h-2p1h terms; the particle-particle term is applied
 // separately) with every large contraction one NT product of arranged
-// operands.  The contractions are those of the generic path term by term:
+// operands.  The contractions are those of the generic path term by term,
+// except two t~ products regrouped through the resident
+// H[i][b][Q] = sum_kd t~_ik^bd (kd|Q) (t~ is symmetric under the exchange of
+// its (occupied, virtual) pairs):
 //   D[z][x][j][y] = Y_yxj - 2 Y_xyj   carries (Y_bcj - 2 Y_cbj) of the
 //                   first-order coupling and (Y_baj - 2 Y_abj) Gamma_jb,
-//   F1 = D t~  is added to D before the (jb|Q) product (both feed
-//                   sum_Q (ac|Q) W_cQ),
+//   F1 = D t~  only feeds the (jb|Q) product: (D + F1) B_ov = D (B_ov + H),
+//   R t~ with R = (ac|kd) Y_c is U H^T, U = sum_c Y_c (ac|Q),
 //   F2 = A~ + C~  is written as [z][k][b][d] for its (bd|Q) product,
 //   S2 gets every (z,a)x(i,b) and (i,a)x(z,b) product through an output map.
 template <typename T, typename TB>
@@ -271,14 +276,13 @@ static void sigma_ea_arranged(adc_ctx* c, const T* Y1, const T* Y2, T* S1, T* S2
     ctr<T>(E, T(1), "ab", v.M11, "zb", Y1, T(0), "za", S1);
     // pair tensors of the trial vectors
     T* Dw = slot<T>(E, A_DW, n4);
-    TB *P1 = nullptr, *P2 = nullptr, *D = nullptr, *Pm = nullptr;
+    TB *P1 = nullptr, *P2 = nullptr, *Pm = nullptr;
     if (o3) {
         P1 = slot<TB>(E, A_P1, n4);
         P2 = slot<TB>(E, A_P2, n4);
-        D = slot<TB>(E, A_D, n4);
         Pm = slot<TB>(E, A_PM, n4);
     }
-    ea_pairs<T, TB>(E, Y2, nvec, (int)O, (int)V, P1, P2, D, Pm, Dw);
+    ea_pairs<T, TB>(E, Y2, nvec, (int)O, (int)V, P1, P2, (TB*)nullptr, Pm, Dw);
     // 21: sigma_abi = -sum_Q U[a][z][Q] (ib|Q),  U = sum_c Y_c (ac|Q)
     T* U = slot<T>(E, S_U, (size_t)(V * Z * Q));
     ctr<T>(E, T(1), "zc", Y1, "acQ", v.Bvv, T(0), "azQ", U);
@@ -290,14 +294,13 @@ static void sigma_ea_arranged(adc_ctx* c, const T* Y1, const T* Y2, T* S1, T* S2
     zeroth_order<T>(E, Y2, S2, nvec, O, (int)V, c->eo.p, c->ev.p, -1.0, 1.0);
 
     T* W = slot<T>(E, A_W, (size_t)(Z * V * Q));
+    const T* BW = v.Bov;    // right operand of the (jb|Q) product
     if (o3) {
         const EaOps<T, TB> a = ea_ops(c, (T*)nullptr, (TB*)nullptr);
+        BW = a.BH;
         // sigma_a += sum_jb (Y_baj - 2 Y_abj) Gamma_jb
         gemm_map<T, T>(E, false, true, Z * V, 1, OV, 1.0, Dw, OV, v.gam, OV, 1.0, S1,
                        GemmOut::rowmajor(1));
-        // D + F1, F1[z][b][k][d] = sum_jc D[z][b][j][c] t~_jk^cd
-        gemm_map<TB, T>(E, false, true, Z * V, OV, OV, 1.0, D, OV, a.ttT1, OV, 1.0, Dw,
-                        GemmOut::rowmajor(OV));
         // sigma_a -= sum_jkl Y_bcj t_kl^bc [2 (jl|ka) - (jk|la)]
         T* X1 = slot<T>(E, A_X1, (size_t)(Z * O * O * O));
         gemm_map<T, T>(E, false, true, Z * O, O * O, VV, 1.0, Y2, VV, v.t, VV, 0.0, X1,
@@ -322,11 +325,9 @@ static void sigma_ea_arranged(adc_ctx* c, const T* Y1, const T* Y2, T* S1, T* S2
                         omap(0, 0, O * O * O, O * O, 1, O));
         gemm_map<TB, T>(E, false, true, Z * O, VV, O * O, -1.0, X, O * O, a.tT, O * O, 1.0, S2,
                         GemmOut::rowmajor(VV));
-        // R[z][a][k][d] = (ac|kd) Y_c:  sigma_abi -= R t~_ik^bd
-        TB* R = slot<TB>(E, A_R, n4);
-        gemm_map<T, TB>(E, false, true, V * Z, OV, Q, 1.0, U, Q, v.Bov, Q, 0.0, R,
-                        omap(Z, OV, OVV, 0, 0, 1));
-        gemm_map<TB, T>(E, false, true, Z * V, OV, OV, -1.0, R, OV, a.ttT1, OV, 1.0, S2, S2_zaib);
+        // sigma_abi -= sum_kd [(ac|kd) Y_c] t~_ik^bd = sum_Q U[a][z][Q] H[i][b][Q]
+        gemm_map<T, T>(E, false, true, V * Z, OV, Q, -1.0, U, Q, a.H, Q, 1.0, S2,
+                       omap(Z, V, OVV, V, VV, 1));
         // R'[z][a][k][d] = (kc|ad) Y_c:  sigma_abi += R' t_ik^bd + R'[z][b] t_ik^da
         T* Wk = slot<T>(E, A_WK, (size_t)(Z * O * Q));
         ctr<T>(E, T(1), "zc", Y1, "kcQ", v.Bov, T(0), "zkQ", Wk);
@@ -340,8 +341,9 @@ static void sigma_ea_arranged(adc_ctx* c, const T* Y1, const T* Y2, T* S1, T* S2
         gemm_map<TB, T>(E, false, true, Z * V, OV, OV, -1.0, P1, OV, a.oovvT, OV, 1.0, S2, S2_zaib);
         gemm_map<TB, T>(E, false, true, OV, Z * V, OV, -1.0, a.oovvT, OV, P2, OV, 1.0, S2, S2_iazb);
     }
-    // sigma_a += sum_cQ (ac|Q) W[z][c][Q],  W = sum_jb (D + F1)[z][c][j][b] (jb|Q)
-    gemm_map<T, T>(E, false, false, Z * V, Q, OV, 1.0, Dw, OV, v.Bov, Q, 0.0, W,
+    // sigma_a += sum_cQ (ac|Q) W[z][c][Q],  W = sum_jb D[z][c][j][b] [(jb|Q) + H_jb^Q]
+    // (ADC(2): no H)
+    gemm_map<T, T>(E, false, false, Z * V, Q, OV, 1.0, Dw, OV, BW, Q, 0.0, W,
                    GemmOut::rowmajor(Q));
     gemm_map<T, T>(E, false, true, Z, V, V * Q, 1.0, W, V * Q, v.Bvv, V * Q, 1.0, S1,
                    GemmOut::rowmajor(V));
@@ -541,7 +543,7 @@ void sigma_cost(const adc_ctx* c, int nvec, double* total, double* pp) {
     if (c->kind == ADC_EA) {
         t = n * (2 * V * V + 6 * O * V * V * Q + 4 * V * V * Q);
         if (c->order == 3) {
-            t += n * (18 * O * O * V * V * V + 8 * O * V * V * Q + 2 * V * V * Q +
+            t += n * (14 * O * O * V * V * V + 8 * O * V * V * Q + 2 * V * V * Q +
                       4 * O * O * O * V * V + 6 * O * O * O * V + 4 * O * V * Q + 6 * O * V * V);
             p = 2 * n * O * V * V * V * V + Q * V * V * (V * V + 1);
         }
