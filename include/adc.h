@@ -101,8 +101,8 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
  *                 particle-particle term (default 16384); a smaller slab means
  *                 more, smaller rebuild blocks
  *   "pp_blocks"   minimum number of blocks of a in that rebuild (default 0:
- *                 min(24, V/8) in FP64, min(12, V/8) at the reduced-precision
- *                 levels); block k
+ *                 min(24, V/8) in FP64 and FP32, min(12, V/8) in BF16);
+ *                 block k
  *                 rebuilds only the pairs b >= its first a, so more blocks
  *                 mean fewer rebuilt flops but smaller products
  *   "pp_group"    blocks of that rebuild contracted together in one product

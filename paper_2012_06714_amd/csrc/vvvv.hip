@@ -59,11 +59,11 @@ void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx) {
     ta_max = std::min(ta_max, V);
     // more blocks rebuild fewer mirrored pairs (Naux V^3 (V + na) flops) but
     // make smaller rebuild products: at least pp_blocks of them (default 24
-    // blocks of at least 8 values of a in FP64, whose products run near the
-    // matrix-core peak at any size; 12 at the reduced levels, whose short-K
+    // blocks of at least 8 values of a in FP64 and FP32, whose products run
+    // near the matrix-core peak at any size; 12 in BF16, whose short-K
     // rebuild is bound by its stores)
     const long long want = c->pp_blocks > 0 ? c->pp_blocks
-                                            : std::min<long long>(sizeof(T) == 8 ? 24 : 12, V / 8);
+                                            : std::min<long long>(sizeof(T) == 2 ? 12 : 24, V / 8);
     const long long nblk = std::min(V, std::max((V + ta_max - 1) / ta_max, want));
     const long long ta = (V + nblk - 1) / nblk;            // balanced a-blocks
     // the contraction runs per group of up to pp_group consecutive blocks
