@@ -7,15 +7,18 @@
 // (ac|bd) = (bd|ac), so for a block A = [a0, a0+na) only the columns b >= a0
 // are rebuilt: one matrix-core GEMM over Q,
 //   rows (a, c) of B_vv (a in A)  x  rows (b, d) of B_vv (b >= a0),
-// whose epilogue scatters the result into the slab K[a][b][c][d].  The slab
-// then serves the direct and the mirrored pairs in one GEMM, contiguous in the
+// whose epilogue scatters the result into a slab K[a-s0][b-s0][c][d] shared by
+// a group of consecutive blocks starting at s0.  The slab then serves the
+// direct and the mirrored pairs in one GEMM per group, contiguous in the
 // summed pair, over the stacked inputs [in; inT] (inT[x][c][d] = in[x][d][c]):
-//   D[x][a][b] = sum_(cd) in[x][(c,d)]  K[a][b][(c,d)]          (b >= a0)
+//   D[x][a][b] = sum_(cd) in[x][(c,d)]  K[a][b][(c,d)]          (b >= s0)
 //   T[x][a][b] = sum_(cd) inT[x][(c,d)] K[a][b][(c,d)] = out[x][b][a]
 // and out takes D where b lies at or past the first a of a's block, else the
-// mirror T[x][b][a] written by the earlier block of b.  The rebuild of a block costs 2 Naux na V^2 (V - a0)
-// flops, Naux V^3 (V + na) over all blocks of size na instead of 2 Naux V^4;
-// the contraction 2 nx V^4 as before.
+// mirror T[x][b][a] written by the group of b (the pairs b in [s0, a0) of a
+// group's later blocks are multiplied but never rebuilt nor used).  The
+// rebuild of a block costs 2 Naux na V^2 (V - a0) flops, Naux V^3 (V + na)
+// over all blocks of size na instead of 2 Naux V^4; the contraction
+// 2 nx V^4 plus the unused pairs of the groups.
 #include "context.hpp"
 
 #include <algorithm>

@@ -40,4 +40,7 @@ def test_host_validation_without_gpu():
     assert lib.adc_sigma(None, dummy, dummy, 1) == adc.ADC_E_ARG
     assert lib.adc_davidson(None, 1, None, None, None, None) == adc.ADC_E_ARG
     assert lib.adc_dim(None) == -1
+    used, peak = ctypes.c_longlong(-7), ctypes.c_longlong(-7)
+    assert lib.adc_workspace(None, ctypes.byref(used), ctypes.byref(peak)) == adc.ADC_E_ARG
+    assert used.value == -7 and peak.value == -7
     lib.adc_destroy(None)
