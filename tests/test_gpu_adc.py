@@ -174,13 +174,13 @@ def test_ea_sigma_both_contraction_paths(order, layout):
     assert 1e-12 < rel32.max() < 1e-5, rel32
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_pp_term_blocked_rebuild(precision):
-    """EA-ADC(3) rebuilt in blocks of a (the default block count, and a slab
-    too small for all a), each block's columns b >= a0 only, with mirrored
-    products for b beyond the block.  Must equal the single-block result
-    (FP64: to rounding; mixed: the same BF16 products summed in another
-    order)."""
+    """EA-ADC(3) rebuilt in blocks of a (the default block count, several
+    counts and groups of blocks per contraction, and a slab too small for all
+    a), each block's columns b >= a0 only, with mirrored products for b beyond
+    the block.  Must equal the single-block result (FP64: to rounding; reduced
+    levels: the same products summed in another order)."""
     from oracle.radc import RADC
     from synthetic import random_vectors, small_system
     O, V, Q, seed = 4, 53, 120, 8
@@ -191,16 +191,24 @@ def test_pp_term_blocked_rebuild(precision):
     X = torch.tensor(random_vectors(ctx.dim, 3, seed + 400), device="cuda")
     ctx.set_option("pp_blocks", 1)
     one = ctx.sigma(X).cpu().numpy()
+    variants = []
+    for blocks, group in [(0, 0), (0, 1), (0, 2), (13, 3), (53, 0)]:
+        ctx.set_option("pp_blocks", blocks)
+        ctx.set_option("pp_group", group)
+        variants.append(ctx.sigma(X).cpu().numpy())
     ctx.set_option("pp_blocks", 0)
-    default = ctx.sigma(X).cpu().numpy()
+    ctx.set_option("pp_group", 0)
     slab_mb = 8 * V ** 3 * 7 / 2 ** 20 * (1 if precision == 0 else 0.25)
     ctx.set_option("pp_slab_mb", max(1, int(slab_mb)))
     blocked = ctx.sigma(X).cpu().numpy()
+    ws = ctx.workspace()
     ctx.close()
+    assert 0 < ws["used"] <= ws["peak"]
     scale = np.abs(one).max()
-    tol = 1e-12 if precision == 0 else 2e-3
+    tol = {0: 1e-12, 1: 2e-3, 2: 1e-5}[precision]
     assert np.abs(blocked - one).max() <= tol * scale
-    assert np.abs(default - one).max() <= tol * scale
+    for v in variants:
+        assert np.abs(v - one).max() <= tol * scale
     if precision == 0:
         ref = RADC(eps, B, O, 3, "ea").sigma(X.cpu().numpy())
         assert np.abs(blocked - ref).max() <= 1e-11 * np.abs(ref).max()
