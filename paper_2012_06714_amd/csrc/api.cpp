@@ -107,6 +107,9 @@ int adc_set_option(adc_ctx* c, const char* key, double value) {
     } else if (k == "tol_r") {
         if (value <= 0) return fail(c, ADC_E_ARG, "tol_r must be > 0");
         c->tol_r = value;
+    } else if (k == "eigensolver") {
+        if (value != 0 && value != 1) return fail(c, ADC_E_ARG, "eigensolver: 0 or 1");
+        c->eigensolver = (int)value;
     } else if (k == "verbose") {
         if (value < 0 || value > 2) return fail(c, ADC_E_ARG, "verbose: 0, 1 or 2");
         c->verbose = (int)value;

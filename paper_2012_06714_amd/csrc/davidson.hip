@@ -323,7 +323,7 @@ struct Solver {
         d.th.alloc(max_space, &c->arena);
         d.ev_e.alloc(max_space, &c->arena);
         d.sel_d.alloc(block, &c->arena);
-        d.info.alloc(1, &c->arena);
+        d.info.alloc(2, &c->arena);   // status, Jacobi sweeps
         initial_space();
         theta_old.assign(block, INFINITY);
         theta.assign(max_space, 0.0);
@@ -446,8 +446,13 @@ struct Solver {
             for (int j = 0; j < m; ++j) Gc[(size_t)i * m + j] = Gh[(size_t)i * max_space + j];
         ADC_HIP(hipMemcpyAsync(d.S.p, Gc.data(), Gc.size() * sizeof(double),
                                hipMemcpyHostToDevice, E.stream));
-        ADC_BLAS(rocsolver_dsyevd(E.blas, rocblas_evect_original, rocblas_fill_upper, m, d.S.p, m,
-                                  d.th.p, d.ev_e.p, d.info.p));
+        if (c->eigensolver == 1)
+            ADC_BLAS(rocsolver_dsyevj(E.blas, rocblas_esort_ascending, rocblas_evect_original,
+                                      rocblas_fill_upper, m, d.S.p, m, 0.0, d.ev_e.p, 100,
+                                      d.info.p + 1, d.th.p, d.info.p));
+        else
+            ADC_BLAS(rocsolver_dsyevd(E.blas, rocblas_evect_original, rocblas_fill_upper, m,
+                                      d.S.p, m, d.th.p, d.ev_e.p, d.info.p));
         ADC_HIP(hipMemcpyAsync(theta.data(), d.th.p, m * sizeof(double), hipMemcpyDeviceToHost,
                                E.stream));
         nbk = std::min(block, m);
