@@ -99,6 +99,26 @@ def test_davidson_matches_dense(O, V, Q, seed, kind, order):
     ctx.close()
 
 
+@pytest.mark.parametrize("kind", ["ea", "ip"])
+def test_davidson_jacobi_eigensolver(kind):
+    """The projected eigenproblem by cyclic Jacobi instead of divide and
+    conquer: the same roots as dense diagonalisation of the oracle's matrix."""
+    from oracle.radc import RADC
+    from synthetic import small_system
+    O, V, Q, seed = SIZES[1]
+    eps, B = small_system(O, V, Q, seed)
+    _say(f"case davidson jacobi {kind}")
+    w = np.linalg.eigvalsh(RADC(eps, B, O, 3, kind).explicit())
+    ctx = _ctx(eps, B, O, 3, kind)
+    ctx.set_option("tol_e", 1e-10)
+    ctx.set_option("tol_r", 1e-6)
+    ctx.set_option("eigensolver", 1)
+    e, P, vecs, it, conv = ctx.davidson(4)
+    ctx.close()
+    assert conv
+    assert np.abs(np.array(e) - w[:4]).max() < 1e-8
+
+
 def test_ip_adc2_o5v19_workload():
     """IP-ADC(2), O=5, V=19, Naux=72: 4 roots by Davidson (tol 1e-8) against
     the explicit 480 x 480 matrix of the oracle."""
