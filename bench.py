@@ -65,7 +65,7 @@ def bench_batch(args):
     (O ~ U{10..40}, V ~ U{8O..12O}, Naux = 3V), in groups of `group` systems
     resident together.  Each group is solved in lockstep (sigma of every
     active system replayed from its own captured graph, issued over four
-    streams), then concurrently (eight host threads, each running the
+    streams), then concurrently (`threads` host threads, each running the
     single-system solver on the next system on a stream of its own), then
     one after another with the single-system solver (graphs on as well).
     value = systems solved per second by the faster of the two batched modes
@@ -113,7 +113,8 @@ def bench_batch(args):
         log(f"bench: systems {g0}..{g0 + len(ctxs) - 1}: lockstep solve {dt:.2f} s, "
             f"{stats['iterations']} iterations, per system {int(np.min(it))}..{int(np.max(it))}")
         t0 = time.perf_counter()
-        ec, _, _, stc, _ = adc.batch_davidson(ctxs, nroots, use_graph=True, concurrent=True)
+        ec, _, _, stc, _ = adc.batch_davidson(ctxs, nroots, use_graph=True, concurrent=True,
+                                              threads=args.threads)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         t_conc += dt
@@ -149,7 +150,7 @@ def bench_batch(args):
                      "captures": captures, "sigma_tflops": fl_batch / t_batch / 1e12,
                      "converged": converged, "system_iterations": [min(sys_its), max(sys_its),
                                                                     float(np.mean(sys_its))]},
-        "concurrent": {"seconds": t_conc, "threads": 8},
+        "concurrent": {"seconds": t_conc, "threads": args.threads},
         "one_by_one": {"seconds": t_seq, "lockstep_speedup": t_seq / t_batch,
                        "concurrent_speedup": t_seq / t_conc,
                        "max_energy_difference_Eh": dev_e},
@@ -175,6 +176,8 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--systems", type=int, default=64, help="batched workload: number of systems")
+    ap.add_argument("--threads", type=int, default=8,
+                    help="batched workload: host threads of the concurrent mode")
     ap.add_argument("--group", type=int, default=16,
                     help="batched workload: systems resident and solved together")
     ap.add_argument("--max-nocc", type=int, default=None,

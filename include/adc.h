@@ -216,11 +216,12 @@ int adc_workspace(const adc_ctx* ctx, long long* used, long long* peak);
  * configured as for adc_davidson.  flags:
  *   bit 0 (1): sigma replayed from each system's own captured graphs (one per
  *              vector count and precision, reused across iterations);
- *   bit 1 (2): concurrent instead of lockstep: up to 8 host threads each run
- *              the single-system solver on the next unsolved system, on a
+ *   bit 1 (2): concurrent instead of lockstep: host threads each run the
+ *              single-system solver on the next unsolved system, on a
  *              stream of its own when the context uses the null stream, so
  *              that the host work of one solve overlaps the device work of
- *              the others.
+ *              the others;
+ *   bits 8-15: number of those threads, 1..64 (0: 8).
  * Without bit 1 the solvers advance in lockstep and each iteration applies
  * sigma to the new trial vectors of every active system, issued back to back
  * over a few default-priority streams.  Results equal those of adc_davidson

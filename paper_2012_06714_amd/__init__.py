@@ -94,9 +94,9 @@ def _dev(x, torch, dtype=None):
     return ctypes.c_void_p(x.data_ptr())
 
 
-def batch_davidson(contexts, nroots, use_graph=True, concurrent=False):
+def batch_davidson(contexts, nroots, use_graph=True, concurrent=False, threads=0):
     """Solve several systems together (adc_batch_davidson): in lockstep, or
-    concurrently on host threads (concurrent=True).  Returns
+    concurrently on host threads (concurrent=True; `threads` of them, 0: 8).  Returns
     (energies [nsys][nroots], P [nsys][nroots], iterations [nsys],
     statuses [nsys], stats {iterations, graph_launches, captures})."""
     import numpy as np
@@ -108,7 +108,8 @@ def batch_davidson(contexts, nroots, use_graph=True, concurrent=False):
     it = np.zeros(n, dtype=np.int32)
     st = np.zeros(n, dtype=np.int32)
     stats = np.zeros(3, dtype=np.int64)
-    rc = lib.adc_batch_davidson(arr, n, int(nroots), int(bool(use_graph)) | (2 if concurrent else 0),
+    flags = int(bool(use_graph)) | (2 if concurrent else 0) | (int(threads) << 8)
+    rc = lib.adc_batch_davidson(arr, n, int(nroots), flags,
                                 e.ctypes.data_as(ctypes.c_void_p), P.ctypes.data_as(ctypes.c_void_p),
                                 it.ctypes.data_as(ctypes.c_void_p), st.ctypes.data_as(ctypes.c_void_p),
                                 stats.ctypes.data_as(ctypes.c_void_p))

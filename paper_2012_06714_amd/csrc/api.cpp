@@ -383,8 +383,11 @@ int adc_mlp_adam(adc_ctx* c, float* params, const float* grad, float* m, float* 
 int adc_batch_davidson(adc_ctx* const* ctxs, int nsys, int nroots, int flags,
                        double* energies, double* spec_factors, int* n_iter, int* status,
                        long long* stats) {
-    if (!ctxs || nsys < 1 || nroots < 1 || !energies || flags < 0 || flags > 3)
+    // bits 0-1: graph, concurrent; bits 8-15: host threads of the concurrent mode
+    if (!ctxs || nsys < 1 || nroots < 1 || !energies || flags < 0 || (flags & ~0xFF03) != 0)
         return fail(nullptr, ADC_E_ARG, "adc_batch_davidson: bad arguments");
+    const int nthreads = ((flags >> 8) & 0xFF) ? ((flags >> 8) & 0xFF) : 8;
+    if (nthreads > 64) return fail(nullptr, ADC_E_ARG, "adc_batch_davidson: at most 64 threads");
     for (int k = 0; k < nsys; ++k) {
         if (!ctxs[k]) return fail(nullptr, ADC_E_ARG, "adc_batch_davidson: NULL context");
         if (nroots > ctxs[k]->dim)
@@ -404,7 +407,7 @@ int adc_batch_davidson(adc_ctx* const* ctxs, int nsys, int nroots, int flags,
             long long c0 = 0;
             for (int k = 0; k < nsys; ++k) c0 += ctxs[k]->graph_captures;
             std::vector<int> its(nsys);
-            int rc = adc::batch_concurrent(ctxs, nsys, nroots, use_graph, 8, energies,
+            int rc = adc::batch_concurrent(ctxs, nsys, nroots, use_graph, nthreads, energies,
                                            spec_factors, its.data(), status);
             if (n_iter)
                 for (int k = 0; k < nsys; ++k) n_iter[k] = its[k];

@@ -43,4 +43,9 @@ def test_host_validation_without_gpu():
     used, peak = ctypes.c_longlong(-7), ctypes.c_longlong(-7)
     assert lib.adc_workspace(None, ctypes.byref(used), ctypes.byref(peak)) == adc.ADC_E_ARG
     assert used.value == -7 and peak.value == -7
+    arr = (ctypes.c_void_p * 1)(8)
+    e = (ctypes.c_double * 1)()
+    # flag bits outside graph/concurrent/thread count, and more than 64 threads
+    assert lib.adc_batch_davidson(arr, 1, 1, 4, e, None, None, None, None) == adc.ADC_E_ARG
+    assert lib.adc_batch_davidson(arr, 1, 1, 2 | (65 << 8), e, None, None, None, None) == adc.ADC_E_ARG
     lib.adc_destroy(None)

@@ -55,13 +55,15 @@ def test_batch_matches_single_solves(precision):
         e, P, _, it, ok = c.davidson(3, want_vectors=False)
         ref.append((np.array(e), np.array(P), it, ok))
         c.close()
-    for use_graph, concurrent in ((True, False), (False, False), (True, True), (False, True)):
+    for use_graph, concurrent, threads in ((True, False, 0), (False, False, 0), (True, True, 0),
+                                           (False, True, 0), (True, True, 2)):
         ctxs = _contexts(systems, precision)
         e, P, it, st, stats = adc.batch_davidson(ctxs, 3, use_graph=use_graph,
-                                                 concurrent=concurrent)
+                                                 concurrent=concurrent, threads=threads)
         for c in ctxs:
             c.close()
-        _say(f"graph={use_graph} concurrent={concurrent} stats {stats} iterations {list(it)}")
+        _say(f"graph={use_graph} concurrent={concurrent} threads={threads} stats {stats} "
+             f"iterations {list(it)}")
         for k, (e0, P0, it0, ok0) in enumerate(ref):
             assert ok0 and st[k] == 0
             assert it[k] == it0
