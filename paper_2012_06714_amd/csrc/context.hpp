@@ -125,7 +125,7 @@ void sigma_block(adc_ctx* c, const double* X, double* Y, int nvec);
 
 // vvvv.hip: out[x][a][b] = sum_cd (ac|bd) in[x][c][d], (ac|bd) rebuilt from B_vv
 template <typename T, typename TO>
-void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx);
+void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx, int npair = 0);
 void sigma(adc_ctx* c, const double* X, double* Y, int nvec, int precision);
 void sigma_eager(adc_ctx* c, const double* X, double* Y, int nvec, int precision);  // one block
 void drop_graphs(adc_ctx* c);

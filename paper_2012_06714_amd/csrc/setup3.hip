@@ -183,7 +183,9 @@ void setup_adc3(adc_ctx* c, const double* tt, const double* X1) {
     // ---- particle-particle ladder and second-order doubles --------------------------
     Buf Lb, Ltb;
     double* Lam = Lb.get(c, OO * VV);
-    vvvv_apply<double, double>(c, Bvv, t, Lam, (long long)OO);   // Lambda_ij^ab = (ac|bd) t_ij^cd
+    // Lambda_ij^ab = (ac|bd) t_ij^cd; t_ij^cd = t_ji^dc, so the mirrored products are rows
+    // of the direct ones
+    vvvv_apply<double, double>(c, Bvv, t, Lam, (long long)OO, O);
     c->u.alloc(OO * VV, &c->arena);
     double* u = c->u.p;
     ctr<double>(E, 1.0, "klba", t, "likj", oooo, 0.0, "ijab", u);

@@ -53,8 +53,37 @@ __global__ void k_pp_assemble(const TO* __restrict__ D, const TO* __restrict__ T
     }
 }
 
+// Pair-symmetric inputs, in[(i,j)][c][d] = in[(j,i)][d][c] (x = i np + j):
+// then out[(i,j)][p][q] = out[(j,i)][q][p], so the mirrored products are rows
+// of the direct ones.  Only the direct results (q at or past the first a of
+// p's block) are computed; this kernel fills the rest of out in place from
+// them (it reads only direct entries and writes only the others).
+template <typename TO>
+__global__ void k_pp_mirror(TO* __restrict__ out, int V, int ta, int np, int nt) {
+    __shared__ TO tile[32][33];
+    const int p0 = (blockIdx.x / nt) * 32, q0 = (blockIdx.x % nt) * 32;
+    const int plast = min(p0 + 31, V - 1);
+    if ((plast / ta) * ta <= q0) return;           // the whole tile is direct
+    const long long x = blockIdx.y;
+    const long long i = x / np, j = x - i * np, xs = j * np + i;
+    const long long VV = (long long)V * V;
+    const TO* src = out + xs * VV;
+    TO* dst = out + x * VV;
+    const int tx = threadIdx.x, ty = threadIdx.y;   // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const int q = q0 + r, p = p0 + tx;
+        const bool need = p < V && q < V && q < (p / ta) * ta;
+        tile[r][tx] = need ? src[(long long)q * V + p] : TO(0);   // out[xs][q][p]
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int p = p0 + r, q = q0 + tx;
+        if (p < V && q < V && q < (p / ta) * ta) dst[(long long)p * V + q] = tile[tx][r];
+    }
+}
+
 template <typename T, typename TO>
-void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx) {
+void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx, int npair) {
     Engine& E = c->E;
     const long long V = c->V, Q = c->Q, VV = V * V, V3 = VV * V;
     if (nx <= 0) return;
@@ -80,10 +109,13 @@ void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx) {
     // several blocks: the inputs stacked as [in; inT] (inT[x][c][d] = in[x][d][c])
     // so that one product per group serves the direct and the mirrored pairs,
     // reading the slab once; its results D (rows 0..nx-1) and T (rows nx..)
-    // are assembled into out at the end
+    // are assembled into out at the end.  Pair-symmetric inputs need only D,
+    // written straight into out and mirrored there.
+    ADC_REQUIRE(npair == 0 || (long long)npair * npair == nx, "particle-particle term: pair count");
+    const bool sym = npair > 0 && nblk > 1;
     T* AB = nullptr;
     TO* DT = nullptr;
-    if (nblk > 1) {
+    if (nblk > 1 && !sym) {
         AB = (T*)E.scratch.get(29, sizeof(T) * 2 * nx * VV);
         ADC_HIP(hipMemcpyAsync(AB, in, sizeof(T) * nx * VV, hipMemcpyDeviceToDevice, E.stream));
         pair_transform<T, T>(E, in, nx * VV, 0, AB + nx * VV, nx * VV, 0, 1, nx, (int)V, 0.0, 1.0,
@@ -112,15 +144,21 @@ void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx) {
         pairs.csplit = nbs;
         pairs.cs1 = V;
         pairs.cs2 = 1;
-        if (nblk > 1)
+        if (nblk > 1 && !sym)
             gemm_acc<T, T>(E, false, true, 2 * nx, ns * nbs, VV, A(1), AB, VV, K, VV, A(0),
                            DT + s0 * V + s0, pairs, 2);
         else
             gemm_acc<T, T>(E, false, true, nx, ns * nbs, VV, A(1), in, VV, K, VV, A(0),
                            out + s0 * V + s0, pairs, 2);
-        E.gemm_flops += 2LL * (nblk > 1 ? 2 : 1) * nx * ns * nbs * VV;
+        E.gemm_flops += 2LL * (nblk > 1 && !sym ? 2 : 1) * nx * ns * nbs * VV;
     }
-    if (nblk > 1) {
+    if (sym) {
+        const int nt = (int)((V + 31) / 32);
+        ADC_REQUIRE(nx <= 65535, "particle-particle term: too many rows");
+        hipLaunchKernelGGL(k_pp_mirror<TO>, dim3((unsigned)(nt * nt), (unsigned)nx), dim3(32, 8),
+                           0, E.stream, out, (int)V, (int)ta, npair, nt);
+        ADC_HIP(hipGetLastError());
+    } else if (nblk > 1) {
         const int nt = (int)((V + 31) / 32);
         ADC_REQUIRE(nx <= 65535, "particle-particle term: too many rows");
         hipLaunchKernelGGL(k_pp_assemble<TO>, dim3((unsigned)(nt * nt), (unsigned)nx),
@@ -130,8 +168,10 @@ void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx) {
 }
 
 template void vvvv_apply<double, double>(adc_ctx*, const double*, const double*, double*,
-                                         long long);
-template void vvvv_apply<bf16_t, float>(adc_ctx*, const bf16_t*, const bf16_t*, float*, long long);
-template void vvvv_apply<float, float>(adc_ctx*, const float*, const float*, float*, long long);
+                                         long long, int);
+template void vvvv_apply<bf16_t, float>(adc_ctx*, const bf16_t*, const bf16_t*, float*, long long,
+                                        int);
+template void vvvv_apply<float, float>(adc_ctx*, const float*, const float*, float*, long long,
+                                       int);
 
 }  // namespace adc
