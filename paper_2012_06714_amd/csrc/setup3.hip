@@ -186,6 +186,7 @@ void setup_adc3(adc_ctx* c, const double* tt, const double* X1) {
     // Lambda_ij^ab = (ac|bd) t_ij^cd; t_ij^cd = t_ji^dc, so the mirrored products are rows
     // of the direct ones
     vvvv_apply<double, double>(c, Bvv, t, Lam, (long long)OO, O);
+    E.scratch.clear();   // the rebuilt slab and operand copies are not needed again here
     c->u.alloc(OO * VV, &c->arena);
     double* u = c->u.p;
     ctr<double>(E, 1.0, "klba", t, "likj", oooo, 0.0, "ijab", u);
@@ -234,6 +235,7 @@ void setup_adc3(adc_ctx* c, const double* tt, const double* X1) {
         else
             m11_third_ip(c, c->M11.p, t, tt, u, Du, Lt, P, P7, Pt, R1, R2, R3);
     }
+    E.scratch.clear();
     Ltb.b.release();
     Dub.b.release();
 
