@@ -123,7 +123,10 @@ void setup_adc3(adc_ctx* c, const double* tt, const double* X1);
 template <typename T, typename TB>
 void sigma_block(adc_ctx* c, const double* X, double* Y, int nvec);
 
-// vvvv.hip: out[x][a][b] = sum_cd (ac|bd) in[x][c][d], (ac|bd) rebuilt from B_vv
+// vvvv.hip: out[x][a][b] = sum_cd (ac|bd) in[x][c][d], (ac|bd) rebuilt from B_vv.
+// npair > 0 declares nx = npair^2 rows x = i npair + j with
+// in[(i,j)][c][d] = in[(j,i)][d][c] (the caller guarantees it); the mirrored
+// products are then taken from the direct ones instead of being computed.
 template <typename T, typename TO>
 void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx, int npair = 0);
 void sigma(adc_ctx* c, const double* X, double* Y, int nvec, int precision);
