@@ -104,9 +104,8 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
  *                 more, smaller rebuild blocks
  *   "pp_blocks"   minimum number of blocks of a in that rebuild (default 0:
  *                 min(24, V/8) in FP64 and FP32, min(12, V/8) in BF16);
- *                 block k
- *                 rebuilds only the pairs b >= its first a, so more blocks
- *                 mean fewer rebuilt flops but smaller products
+ *                 block k rebuilds only the pairs b >= its first a, so more
+ *                 blocks mean fewer rebuilt flops but smaller products
  *   "pp_group"    blocks of that rebuild contracted together in one product
  *                 (default 0: 8, bounded by the slab size)
  *   "workspace_limit"  bytes the context may allocate in total
@@ -119,7 +118,8 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
  *                 the fastest (default), 2 = as 1 and log the choices
  *   "ea_layout"   EA sigma: 1 = keep the amplitudes and integrals of the
  *                 2p1h rows also in product-ready layouts (six extra
- *                 O^2 V^2 FP64 tensors, seven BF16 ones in the mixed mode)
+ *                 O^2 V^2 FP64 tensors, seven BF16 ones in the mixed mode,
+ *                 and two O V Naux matrices that fold t~ into the coupling)
  *                 so that each large contraction is one matrix-core product,
  *                 0 = generic contractions (permute per call), -1 = 1 when
  *                 the extra tensors fit in half of the free device memory
