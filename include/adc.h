@@ -97,8 +97,11 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
  *                 each root (default sqrt(tol_e))
  *   "verbose"     1: per-iteration line on stderr; 2: also the solver's
  *                 wall time per phase (synchronising after each phase)
- *   "eigensolver" projected Rayleigh-Ritz eigenproblem on the device:
- *                 0 = divide and conquer (default), 1 = cyclic Jacobi
+ *   "eigensolver" projected Rayleigh-Ritz eigenproblem: 0 = automatic
+ *                 (default: 2 up to 128 basis vectors, else 3), 1 = rocSOLVER
+ *                 cyclic Jacobi, 2 = Householder tridiagonalisation and
+ *                 implicit QR on the host, where the projected matrix is
+ *                 assembled, 3 = rocSOLVER divide and conquer
  *   "pp_slab_mb"  size bound in MiB of the rebuilt four-virtual slab of the
  *                 particle-particle term (default 16384); a smaller slab means
  *                 more, smaller rebuild blocks

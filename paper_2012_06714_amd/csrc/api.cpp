@@ -108,7 +108,8 @@ int adc_set_option(adc_ctx* c, const char* key, double value) {
         if (value <= 0) return fail(c, ADC_E_ARG, "tol_r must be > 0");
         c->tol_r = value;
     } else if (k == "eigensolver") {
-        if (value != 0 && value != 1) return fail(c, ADC_E_ARG, "eigensolver: 0 or 1");
+        if (value != 0 && value != 1 && value != 2 && value != 3)
+            return fail(c, ADC_E_ARG, "eigensolver: 0, 1, 2 or 3");
         c->eigensolver = (int)value;
     } else if (k == "verbose") {
         if (value < 0 || value > 2) return fail(c, ADC_E_ARG, "verbose: 0, 1 or 2");

@@ -22,7 +22,7 @@ struct adc_ctx {
     double tol_e = 1e-8;
     double tol_r = -1.0;   // <0: sqrt(tol_e)
     int verbose = 0;
-    int eigensolver = 0;   // projected eigenproblem: 0 divide and conquer, 1 Jacobi
+    int eigensolver = 0;   // projected eigenproblem: 0 auto, 1 Jacobi, 2 host QR, 3 divide and conquer
 
     adc::Arena arena;
     adc::Engine E;

@@ -31,6 +31,8 @@
 
 #include <rocsolver/rocsolver.h>
 
+#include "syev_host.hpp"
+
 #include <algorithm>
 #include <cfloat>
 #include <chrono>
@@ -279,7 +281,7 @@ struct Solver {
     const double rel_switch = 3e-3;
     Dav d;
     clk::time_point t0;
-    std::vector<double> theta_old, theta, rnorm, Gh, blk;
+    std::vector<double> theta_old, theta, rnorm, Gh, blk, Sh;
     int it = 0, status = ADC_OK, m = 0, newstart = 0, nbk = 0;
     int stage = 0;    // sigma level of the current phase: 1 BF16, 2 FP32 products, 0 FP64
     bool use_mlp, done = false;
@@ -440,21 +442,33 @@ struct Solver {
             }
         }
         newstart = m;
-        // projected eigenproblem (rocSOLVER, column-major == row-major for symmetric input)
+        // projected eigenproblem: on the host (the matrix is there already), or by
+        // rocSOLVER (column-major == row-major for symmetric input)
         std::vector<double> Gc((size_t)m * m);
         for (int i = 0; i < m; ++i)
             for (int j = 0; j < m; ++j) Gc[(size_t)i * m + j] = Gh[(size_t)i * max_space + j];
-        ADC_HIP(hipMemcpyAsync(d.S.p, Gc.data(), Gc.size() * sizeof(double),
-                               hipMemcpyHostToDevice, E.stream));
-        if (c->eigensolver == 1)
-            ADC_BLAS(rocsolver_dsyevj(E.blas, rocblas_esort_ascending, rocblas_evect_original,
-                                      rocblas_fill_upper, m, d.S.p, m, 0.0, d.ev_e.p, 100,
-                                      d.info.p + 1, d.th.p, d.info.p));
-        else
-            ADC_BLAS(rocsolver_dsyevd(E.blas, rocblas_evect_original, rocblas_fill_upper, m,
-                                      d.S.p, m, d.th.p, d.ev_e.p, d.info.p));
-        ADC_HIP(hipMemcpyAsync(theta.data(), d.th.p, m * sizeof(double), hipMemcpyDeviceToHost,
-                               E.stream));
+        const bool on_host = c->eigensolver == 2 || (c->eigensolver == 0 && m <= 128);
+        if (on_host) {
+            Sh.resize((size_t)m * m);
+            if (!syev_host(m, Gc.data(), theta.data(), Sh.data()))
+                throw Error(ADC_E_NUMERIC, "projected eigenproblem: QR sweeps did not converge");
+            ADC_HIP(hipMemcpyAsync(d.S.p, Sh.data(), Sh.size() * sizeof(double),
+                                   hipMemcpyHostToDevice, E.stream));
+            ADC_HIP(hipMemcpyAsync(d.th.p, theta.data(), m * sizeof(double),
+                                   hipMemcpyHostToDevice, E.stream));
+        } else {
+            ADC_HIP(hipMemcpyAsync(d.S.p, Gc.data(), Gc.size() * sizeof(double),
+                                   hipMemcpyHostToDevice, E.stream));
+            if (c->eigensolver == 1)
+                ADC_BLAS(rocsolver_dsyevj(E.blas, rocblas_esort_ascending, rocblas_evect_original,
+                                          rocblas_fill_upper, m, d.S.p, m, 0.0, d.ev_e.p, 100,
+                                          d.info.p + 1, d.th.p, d.info.p));
+            else
+                ADC_BLAS(rocsolver_dsyevd(E.blas, rocblas_evect_original, rocblas_fill_upper, m,
+                                          d.S.p, m, d.th.p, d.ev_e.p, d.info.p));
+            ADC_HIP(hipMemcpyAsync(theta.data(), d.th.p, m * sizeof(double),
+                                   hipMemcpyDeviceToHost, E.stream));
+        }
         nbk = std::min(block, m);
         // Ritz vectors: X = S^T V, AX = S^T W  (row k of S is eigenvector k)
         gemm_rm<double>(E, false, false, nbk, dim, m, 1.0, d.S.p, m, 0, d.V.p, dim, 0, 0.0, d.X.p,

@@ -99,20 +99,22 @@ def test_davidson_matches_dense(O, V, Q, seed, kind, order):
     ctx.close()
 
 
+@pytest.mark.parametrize("solver", [1, 2, 3])
 @pytest.mark.parametrize("kind", ["ea", "ip"])
-def test_davidson_jacobi_eigensolver(kind):
-    """The projected eigenproblem by cyclic Jacobi instead of divide and
-    conquer: the same roots as dense diagonalisation of the oracle's matrix."""
+def test_davidson_eigensolvers(kind, solver):
+    """The projected eigenproblem by rocSOLVER's cyclic Jacobi (1), the host
+    QR solver (2) or rocSOLVER's divide and conquer (3): the same roots as
+    dense diagonalisation of the oracle's matrix."""
     from oracle.radc import RADC
     from synthetic import small_system
     O, V, Q, seed = SIZES[1]
     eps, B = small_system(O, V, Q, seed)
-    _say(f"case davidson jacobi {kind}")
+    _say(f"case davidson eigensolver {solver} {kind}")
     w = np.linalg.eigvalsh(RADC(eps, B, O, 3, kind).explicit())
     ctx = _ctx(eps, B, O, 3, kind)
     ctx.set_option("tol_e", 1e-10)
     ctx.set_option("tol_r", 1e-6)
-    ctx.set_option("eigensolver", 1)
+    ctx.set_option("eigensolver", solver)
     e, P, vecs, it, conv = ctx.davidson(4)
     ctx.close()
     assert conv
