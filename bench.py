@@ -34,7 +34,7 @@ PEAKS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 # the solver; FP32 products, used by the solver as a middle phase (BF16 ->
 # FP32 -> FP64)
 LEVEL = {"fp64": 0, "mixed": 1, "mixed3": 2}
-PP_TRAFFIC = {("ea-adc3-o20v180", "fp64"): 5.1858e+10, ("ea-adc3-o20v180", "mixed"): 6.0295e+09}
+PP_TRAFFIC = {("ea-adc3-o20v180", "fp64"): 5.1352e+10, ("ea-adc3-o20v180", "mixed"): 5.8496e+09}
 HBM_GBPS = 8000.0
 
 
