@@ -98,7 +98,7 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
  *   "verbose"     1: per-iteration line on stderr; 2: also the solver's
  *                 wall time per phase (synchronising after each phase)
  *   "eigensolver" projected Rayleigh-Ritz eigenproblem: 0 = automatic
- *                 (default: 2 up to 128 basis vectors, else 3), 1 = rocSOLVER
+ *                 (default: 2 up to 64 basis vectors, else 3), 1 = rocSOLVER
  *                 cyclic Jacobi, 2 = Householder tridiagonalisation and
  *                 implicit QR on the host, where the projected matrix is
  *                 assembled, 3 = rocSOLVER divide and conquer

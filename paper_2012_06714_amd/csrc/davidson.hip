@@ -447,10 +447,10 @@ struct Solver {
         std::vector<double> Gc((size_t)m * m);
         for (int i = 0; i < m; ++i)
             for (int j = 0; j < m; ++j) Gc[(size_t)i * m + j] = Gh[(size_t)i * max_space + j];
-        const bool on_host = c->eigensolver == 2 || (c->eigensolver == 0 && m <= 128);
+        const bool on_host = c->eigensolver == 2 || (c->eigensolver == 0 && m <= 64);
         if (on_host) {
             Sh.resize((size_t)m * m);
-            if (!syev_host(m, Gc.data(), theta.data(), Sh.data()))
+            if (!syev_host(m, Gc.data(), theta.data(), Sh.data(), std::min(block, m)))
                 throw Error(ADC_E_NUMERIC, "projected eigenproblem: QR sweeps did not converge");
             ADC_HIP(hipMemcpyAsync(d.S.p, Sh.data(), Sh.size() * sizeof(double),
                                    hipMemcpyHostToDevice, E.stream));

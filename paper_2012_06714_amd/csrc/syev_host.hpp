@@ -15,8 +15,9 @@ namespace adc {
 
 // A: n x n symmetric, row-major (only read).  On success w[k] holds the
 // eigenvalues in ascending order and row k of S (n x n, row-major) the unit
-// eigenvector of w[k].  Returns false when the QR sweeps do not converge.
-inline bool syev_host(int n, const double* A, double* w, double* S) {
+// eigenvector of w[k]; the lowest nref eigenvalues are recomputed as Rayleigh
+// quotients of their vectors.  Returns false when the QR sweeps do not converge.
+inline bool syev_host(int n, const double* A, double* w, double* S, int nref = 0) {
     if (n <= 0) return true;
     // Zt holds the accumulated transformation transposed (row k = column k),
     // so that rotations and reflections touch contiguous rows
@@ -115,10 +116,33 @@ inline bool syev_host(int n, const double* A, double* w, double* S) {
     std::vector<int> ord(n);
     std::iota(ord.begin(), ord.end(), 0);
     std::sort(ord.begin(), ord.end(), [&](int i, int j) { return d[i] < d[j]; });
+    // the lowest nref eigenvalues as Rayleigh quotients s^T A s of the computed
+    // unit vectors: the QR sweeps leave errors of up to a few hundred ulps of
+    // ||A|| on the diagonal, the quotient is accurate to the rounding of the
+    // products
+    nref = std::min(std::max(nref, 0), n);
     for (int k = 0; k < n; ++k) {
+        const double* sk = &Zt[(size_t)ord[k] * n];
+        std::copy_n(sk, n, &S[(size_t)k * n]);
         w[k] = d[ord[k]];
-        std::copy_n(&Zt[(size_t)ord[k] * n], n, &S[(size_t)k * n]);
+        if (k >= nref) continue;
+        double q = 0.0, nn = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double t = 0.0;
+            const double* ai = A + (size_t)i * n;
+            for (int j = 0; j < n; ++j) t += ai[j] * sk[j];
+            q += sk[i] * t;
+            nn += sk[i] * sk[i];
+        }
+        w[k] = q / nn;
     }
+    // keep the ascending order (the quotients can only swap values that agree
+    // to rounding)
+    for (int k = 1; k < nref; ++k)
+        for (int j = k; j > 0 && w[j] < w[j - 1]; --j) {
+            std::swap(w[j], w[j - 1]);
+            std::swap_ranges(&S[(size_t)j * n], &S[(size_t)j * n] + n, &S[(size_t)(j - 1) * n]);
+        }
     return true;
 }
 

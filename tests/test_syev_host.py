@@ -18,7 +18,7 @@ int main() {
     while (std::scanf("%d", &n) == 1) {
         std::vector<double> A((size_t)n * n), w(n), S((size_t)n * n);
         for (auto& x : A) if (std::scanf("%lf", &x) != 1) return 2;
-        if (!adc::syev_host(n, A.data(), w.data(), S.data())) { std::printf("FAIL\n"); continue; }
+        if (!adc::syev_host(n, A.data(), w.data(), S.data(), n)) { std::printf("FAIL\n"); continue; }
         for (double x : w) std::printf("%.17g\n", x);
         for (double x : S) std::printf("%.17g\n", x);
     }
