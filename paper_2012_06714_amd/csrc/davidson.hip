@@ -448,10 +448,9 @@ struct Solver {
         for (int i = 0; i < m; ++i)
             for (int j = 0; j < m; ++j) Gc[(size_t)i * m + j] = Gh[(size_t)i * max_space + j];
         const bool on_host = c->eigensolver == 2 || (c->eigensolver == 0 && m <= 64);
-        if (on_host) {
-            Sh.resize((size_t)m * m);
-            if (!syev_host(m, Gc.data(), theta.data(), Sh.data(), std::min(block, m)))
-                throw Error(ADC_E_NUMERIC, "projected eigenproblem: QR sweeps did not converge");
+        Sh.resize((size_t)m * m);
+        // (rocSOLVER takes over should the host QR sweeps not converge)
+        if (on_host && syev_host(m, Gc.data(), theta.data(), Sh.data(), std::min(block, m))) {
             ADC_HIP(hipMemcpyAsync(d.S.p, Sh.data(), Sh.size() * sizeof(double),
                                    hipMemcpyHostToDevice, E.stream));
             ADC_HIP(hipMemcpyAsync(d.th.p, theta.data(), m * sizeof(double),
