@@ -101,7 +101,8 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
  *                 (default: 2 up to 64 basis vectors, else 3), 1 = rocSOLVER
  *                 cyclic Jacobi, 2 = Householder tridiagonalisation and
  *                 implicit QR on the host, where the projected matrix is
- *                 assembled, 3 = rocSOLVER divide and conquer
+ *                 assembled (3 if its sweeps do not converge), 3 = rocSOLVER
+ *                 divide and conquer
  *   "pp_slab_mb"  size bound in MiB of the rebuilt four-virtual slab of the
  *                 particle-particle term (default 16384); a smaller slab means
  *                 more, smaller rebuild blocks
