@@ -130,6 +130,11 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
  *                 (default)
  *   "ctr_log"     1 = time each generic contraction with HIP events and
  *                 print its product shape on stderr (sigma then runs eagerly)
+ *   "gemm_config" -1 = tile configuration of each matrix-core product chosen
+ *                 by the autotuner or heuristic (default); 0..7 = that
+ *                 configuration forced on every product of this context (ids
+ *                 from adc_gemm_configs; one not compiled for a product's
+ *                 type runs as 0)
  * Errors: ADC_E_ARG for an unknown key or out-of-range value. */
 int adc_set_option(adc_ctx* ctx, const char* key, double value);
 
@@ -139,7 +144,14 @@ int adc_set_stream(adc_ctx* ctx, void* hip_stream);
 /* Dimension of the ADC matrix (see the layout above); -1 for NULL. */
 long long adc_dim(const adc_ctx* ctx);
 
-/* Exact diagonal of M in the Z basis.  d: device [dim] (written). */
+/* Exact diagonal of M in the Z basis (the diagonal that the Davidson
+ * correction of Sec. III.A, step 4, divides by; the paper does not say which
+ * diagonal its solver uses, and this one is exact: the 1p-1p / 1h-1h block's
+ * diagonal through order n and, in the 2p1h / 2h1p block, the zeroth-order
+ * orbital-energy differences plus, for n = 3, the first-order diagonal terms
+ * such as (aa|bb), in the Z basis of the layout above).
+ * d: device [dim] (written; caller-owned).  Errors: ADC_E_ARG for a NULL
+ * context or output, ADC_E_HIP for a failed copy. */
 int adc_diag(adc_ctx* ctx, double* d);
 
 /* sigma = M X for a block of vectors (step 4, Eqs. 36-37 and their EA
@@ -240,6 +252,60 @@ int adc_workspace(const adc_ctx* ctx, long long* used, long long* peak);
 int adc_batch_davidson(adc_ctx* const* ctxs, int nsys, int nroots, int flags,
                        double* energies, double* spec_factors, int* n_iter, int* status,
                        long long* stats);
+
+/* The same batched solve over a batch object that owns its contexts
+ * (step 4 of Sec. III.A over many independent systems; not in the paper).
+ * adc_system_desc: the arguments of adc_setup for one system (eps, B device
+ * pointers, read during adc_setup_batch only).  adc_setup_batch sets up nsys
+ * systems one after another (each as adc_setup; every system's tensors stay
+ * resident, so the batch must fit in device memory together) and returns a
+ * batch that owns them; on any failure it releases the systems already made
+ * and returns that failure's code (message in adc_last_error(NULL)).
+ * adc_batch_set_option applies one option to every system.
+ * adc_davidson_batch solves every system as adc_batch_davidson does on the
+ * batch's contexts (same flags and outputs).  adc_batch_context returns the
+ * k-th context (owned by the batch; NULL when k is out of range), for per-system
+ * options or queries.  adc_batch_destroy releases the batch and its
+ * contexts (NULL is ignored). */
+typedef struct adc_batch adc_batch;
+typedef struct adc_system_desc {
+    const double* eps;   /* device [nocc + nvir]                 */
+    const double* B;     /* device [naux][nocc+nvir][nocc+nvir]  */
+    int nocc, nvir, naux, order, kind;
+} adc_system_desc;
+int adc_setup_batch(int nsys, const adc_system_desc* sys, adc_batch** out);
+int adc_batch_set_option(adc_batch* batch, const char* key, double value);
+int adc_davidson_batch(adc_batch* batch, int nroots, int flags, double* energies,
+                       double* spec_factors, int* n_iter, int* status, long long* stats);
+adc_ctx* adc_batch_context(adc_batch* batch, int k);
+void adc_batch_destroy(adc_batch* batch);
+
+/* The matrix-core product under every contraction of the library, on its
+ * own (not in the paper: exposed so that each compiled tile configuration
+ * can be checked against a reference product):
+ *   C = alpha op(A) op(B) + beta C
+ * ta = 0: A is [M][K] row-major (lda >= K), ta = 1: A is [K][M] (lda >= M);
+ * tb = 1: B is [N][K] (ldb >= K), tb = 0: B is [K][N] (ldb >= N).
+ * dtype: 0 = FP64 throughout; 1 = FP32 operands, products and sums; 2 = FP32
+ * operands rounded to BF16 (nearest even) while staged, BF16 products, FP32
+ * sums; 3 = BF16 operands (A, B as raw 16-bit BF16), FP32 sums.  C: FP64 for
+ * dtype 0, else FP32.  A, B, C: device pointers on `stream` (a hipStream_t,
+ * NULL: the null stream); caller-owned; C must not overlap A or B.
+ * map: NULL for a row-major C with leading dimension ldc, else 6 values
+ * {rsplit, rs1, rs2, csplit, cs1, cs2}: element (m, n) is stored at
+ *   (m / rsplit) rs1 + (m % rsplit) rs2 + (n / csplit) cs1 + (n % csplit) cs2
+ * (a split of 0 means no split: m rs2, n cs2); the caller guarantees every
+ * such offset lies inside C and that distinct (m, n) map to distinct offsets.
+ * config: a tile configuration id from adc_gemm_configs, or -1 for the
+ * library's own choice.  Synchronises the stream before returning.
+ * Errors: ADC_E_ARG (bad dtype, sizes, leading dimensions, map or config),
+ * ADC_E_HIP.  adc_gemm_configs writes the configuration ids compiled for a
+ * dtype into ids (at most 8) and returns their count (ADC_E_ARG for a bad
+ * dtype or NULL ids). */
+int adc_gemm(int dtype, int ta, int tb, long long M, long long N, long long K, double alpha,
+             const void* A, long long lda, const void* B, long long ldb, double beta, void* C,
+             long long ldc, const long long* map, int config, void* stream);
+int adc_gemm_configs(int dtype, int* ids);
 
 /* Number of sigma graph replays so far (option "graph"); -1 for NULL. */
 long long adc_graph_launches(const adc_ctx* ctx);

@@ -134,11 +134,17 @@ class RADC:
                 ops.append(self.T[name])
         return subs, ops
 
-    def _eval(self, terms, out, **kw):
+    def _eval(self, terms, out, magnitude=False, **kw):
+        """Sum of the terms; magnitude=True sums |coef| times the product of
+        the operands' absolute values instead (a bound on every partial sum any
+        regrouping of the same terms can form)."""
         acc = None
         for coef, spec in terms:
             subs, ops = self._operands(spec, **kw)
-            val = float(eval_fraction(coef)) * _einsum_sliced(subs, out, ops)
+            c = float(eval_fraction(coef))
+            if magnitude:
+                c, ops = abs(c), [np.abs(op) for op in ops]
+            val = c * _einsum_sliced(subs, out, ops)
             acc = val if acc is None else acc + val
         return acc
 
@@ -223,21 +229,23 @@ class RADC:
     # ------------------------------------------------------------------
     # step 4: sigma = M Z
     # ------------------------------------------------------------------
-    def sigma_y(self, Y1, Y2, skip_11=False):
+    def sigma_y(self, Y1, Y2, skip_11=False, magnitude=False):
         """Rows of M_Y Y (the non-symmetric representation of Eqs. 36-37).
 
         skip_11 leaves out the 1p-1p / 1h-1h product (used to time the rest
-        without building M11)."""
+        without building M11); magnitude: see sigma_magnitude."""
         if self.kind == "ea":
             e1, e2 = "za", "zabi"
         else:
             e1, e2 = "zi", "zija"
+        M11 = np.abs(self.M11) if magnitude and not skip_11 else None
         if skip_11:
             s1 = np.zeros_like(Y1)
         else:
-            s1 = np.einsum("xy,zy->zx", self.M11, Y1)
-        s1 = s1 + self._eval(self._blocks("12"), e1, Y1=Y1, Y2=Y2)
-        s2 = self._eval(self._blocks("21") + self._blocks("22"), e2, Y1=Y1, Y2=Y2)
+            s1 = np.einsum("xy,zy->zx", M11 if magnitude else self.M11, Y1)
+        s1 = s1 + self._eval(self._blocks("12"), e1, magnitude=magnitude, Y1=Y1, Y2=Y2)
+        s2 = self._eval(self._blocks("21") + self._blocks("22"), e2, magnitude=magnitude,
+                        Y1=Y1, Y2=Y2)
         return s1, s2
 
     def sigma(self, vecs, skip_11=False):
@@ -246,6 +254,21 @@ class RADC:
         Y2 = self.z_to_y(Z2)
         s1, s2 = self.sigma_y(Z1, Y2, skip_11=skip_11)
         return self.pack(s1, self.y_to_z(s2))
+
+    def sigma_magnitude(self, vecs):
+        """Scale for rounding-error bounds of sigma, element by element: the
+        same sums as sigma with every coefficient, tensor, metric factor and
+        vector element replaced by its absolute value, so that each element
+        bounds the absolute values of the products that make up that element
+        of sigma = M_Z X (and of any regrouping of those products).  Not a
+        result of the method: only the scale against which a reduced-precision
+        sigma is compared."""
+        Z1, Z2 = self.unpack(vecs)
+        Z1, Z2 = np.abs(Z1), np.abs(Z2)
+        Y2 = ALI * Z2 + abs(BEI) * Z2.transpose(0, 2, 1, 3)
+        s1, s2 = self.sigma_y(Z1, Y2, magnitude=True)
+        s2 = AL * s2 + abs(BE) * s2.transpose(0, 2, 1, 3)
+        return self.pack(s1, s2)
 
     def explicit(self):
         """Explicit M_Z (dim x dim) by sigma on unit vectors (small cases only)."""

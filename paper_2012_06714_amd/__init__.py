@@ -24,7 +24,9 @@ ABI_SYMBOLS = ("adc_setup", "adc_set_option", "adc_set_stream", "adc_dim", "adc_
                "adc_sigma_timed", "adc_history", "adc_mlp_nparams", "adc_precond_mlp",
                "adc_mlp_status", "adc_mlp_pairs", "adc_mlp_forward", "adc_mlp_loss_grad",
                "adc_mlp_adam", "adc_record_count", "adc_record_get", "adc_graph_launches",
-               "adc_batch_davidson")
+               "adc_batch_davidson", "adc_setup_batch", "adc_batch_set_option",
+               "adc_davidson_batch", "adc_batch_context", "adc_batch_destroy", "adc_gemm",
+               "adc_gemm_configs")
 
 
 class ADCError(RuntimeError):
@@ -66,6 +68,13 @@ def _load():
         "adc_record_get": (i, [vp, i, vp, vp, vp, vp]),
         "adc_graph_launches": (ll, [vp]),
         "adc_batch_davidson": (i, [vp, i, i, i, vp, vp, vp, vp, vp]),
+        "adc_setup_batch": (i, [i, vp, ctypes.POINTER(vp)]),
+        "adc_batch_set_option": (i, [vp, ctypes.c_char_p, d]),
+        "adc_davidson_batch": (i, [vp, i, i, vp, vp, vp, vp, vp]),
+        "adc_batch_context": (vp, [vp, i]),
+        "adc_batch_destroy": (None, [vp]),
+        "adc_gemm": (i, [i, i, i, ll, ll, ll, d, vp, ll, vp, ll, d, vp, ll, vp, i, vp]),
+        "adc_gemm_configs": (i, [i, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -117,6 +126,94 @@ def batch_davidson(contexts, nroots, use_graph=True, concurrent=False, threads=0
         raise ADCError(rc, last_error(None))
     return e, P, it, st, {"iterations": int(stats[0]), "graph_launches": int(stats[1]),
                           "captures": int(stats[2])}
+
+
+def gemm_configs(dtype):
+    """Tile configuration ids compiled for a product type (adc_gemm_configs)."""
+    ids = (ctypes.c_int * 8)()
+    n = lib.adc_gemm_configs(int(dtype), ids)
+    if n < 0:
+        raise ADCError(n, last_error(None))
+    return list(ids[:n])
+
+
+def gemm(dtype, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, omap=None, config=-1):
+    """adc_gemm on torch device tensors (A, B, C: contiguous CUDA tensors of
+    the storage type of `dtype`; BF16 operands as torch.bfloat16)."""
+    import torch
+    st = {0: (torch.float64, torch.float64), 1: (torch.float32, torch.float32),
+          2: (torch.float32, torch.float32), 3: (torch.bfloat16, torch.float32)}[int(dtype)]
+    m = None
+    if omap is not None:
+        m = (ctypes.c_longlong * 6)(*[int(x) for x in omap])
+    _check(lib.adc_gemm(int(dtype), int(ta), int(tb), int(M), int(N), int(K), float(alpha),
+                        _dev(A, torch, st[0]), int(lda), _dev(B, torch, st[0]), int(ldb),
+                        float(beta), _dev(C, torch, st[1]), int(ldc), m, int(config),
+                        ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+
+class _SystemDesc(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_void_p), ("B", ctypes.c_void_p), ("nocc", ctypes.c_int),
+                ("nvir", ctypes.c_int), ("naux", ctypes.c_int), ("order", ctypes.c_int),
+                ("kind", ctypes.c_int)]
+
+
+class Batch:
+    """Several systems owned by one batch object (adc_setup_batch).
+
+    systems: list of (eps [N] CUDA float64, B [Naux, N, N] CUDA float64, nocc,
+    order, kind)."""
+
+    def __init__(self, systems):
+        import torch
+        self._torch = torch
+        n = len(systems)
+        descs = (_SystemDesc * n)()
+        self.dims = []
+        for k, (eps, B, nocc, order, kind) in enumerate(systems):
+            kk = ADC_EA if kind == "ea" else ADC_IP if kind == "ip" else -9
+            descs[k] = _SystemDesc(_dev(eps, torch).value, _dev(B, torch).value, int(nocc),
+                                   int(eps.shape[0]) - int(nocc), int(B.shape[0]), int(order), kk)
+        h = ctypes.c_void_p()
+        _check(lib.adc_setup_batch(n, descs, ctypes.byref(h)))
+        self._h = h
+        self.n = n
+        self.dims = [int(lib.adc_dim(lib.adc_batch_context(h, k))) for k in range(n)]
+
+    def set_option(self, key, value):
+        _check(lib.adc_batch_set_option(self._h, key.encode(), float(value)))
+
+    def davidson(self, nroots, use_graph=True, concurrent=False, threads=0):
+        """adc_davidson_batch: (energies [n][nroots], P, iterations, statuses, stats)."""
+        import numpy as np
+        n = self.n
+        e = np.zeros((n, nroots))
+        P = np.zeros((n, nroots))
+        it = np.zeros(n, dtype=np.int32)
+        st = np.zeros(n, dtype=np.int32)
+        stats = np.zeros(3, dtype=np.int64)
+        flags = int(bool(use_graph)) | (2 if concurrent else 0) | (int(threads) << 8)
+        rc = lib.adc_davidson_batch(self._h, int(nroots), flags,
+                                    e.ctypes.data_as(ctypes.c_void_p),
+                                    P.ctypes.data_as(ctypes.c_void_p),
+                                    it.ctypes.data_as(ctypes.c_void_p),
+                                    st.ctypes.data_as(ctypes.c_void_p),
+                                    stats.ctypes.data_as(ctypes.c_void_p))
+        if rc not in (ADC_OK, ADC_E_NOCONV):
+            raise ADCError(rc, last_error(None))
+        return e, P, it, st, {"iterations": int(stats[0]), "graph_launches": int(stats[1]),
+                              "captures": int(stats[2])}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.adc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Context:

@@ -166,6 +166,7 @@ struct Engine {
     hipEvent_t tev[2] = {nullptr, nullptr};
     bool timing = false;     // record events around the particle-particle kernels
     bool ctr_log = false;    // time every contraction and print its GEMM plan to stderr
+    int force_cfg = -1;      // GEMM tile configuration forced on every product (-1: automatic)
     double pp_ms = 0.0;      // accumulated milliseconds of those kernels
 };
 

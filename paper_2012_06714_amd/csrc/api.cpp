@@ -155,6 +155,12 @@ int adc_set_option(adc_ctx* c, const char* key, double value) {
         // 1: time each contraction of sigma with events and print its plan on stderr
         if (value != 0 && value != 1) return fail(c, ADC_E_ARG, "ctr_log: 0 or 1");
         c->E.ctr_log = value == 1;
+    } else if (k == "gemm_config") {
+        // force one matrix-core tile configuration on every product (-1: automatic)
+        if (value < -1 || value > 7 || value != std::floor(value))
+            return fail(c, ADC_E_ARG, "gemm_config: -1 or a configuration id 0..7");
+        c->E.force_cfg = (int)value;
+        adc::drop_graphs(c);
     } else if (k == "pp_slab_mb") {
         if (value < 1 || value > 1048576) return fail(c, ADC_E_ARG, "pp_slab_mb out of range");
         c->pp_slab_bytes = (long long)(value * 1048576.0);
@@ -305,6 +311,70 @@ int adc_sigma_timed(adc_ctx* c, const double* X, double* Y, int nvec, double* ms
     });
 }
 
+// ---- the matrix-core product on its own ------------------------------------
+int adc_gemm_configs(int dtype, int* ids) {
+    if (!ids) return fail(nullptr, ADC_E_ARG, "adc_gemm_configs: NULL ids");
+    switch (dtype) {
+        case 0: return adc::gemm_candidates<double>(ids);
+        case 1: return adc::gemm_candidates<float>(ids);
+        case 2:
+        case 3: return adc::gemm_candidates<adc::bf16_t>(ids);
+        default: return fail(nullptr, ADC_E_ARG, "adc_gemm_configs: dtype must be 0..3");
+    }
+}
+
+int adc_gemm(int dtype, int ta, int tb, long long M, long long N, long long K, double alpha,
+             const void* A, long long lda, const void* B, long long ldb, double beta, void* C,
+             long long ldc, const long long* map, int config, void* stream) {
+    if (dtype < 0 || dtype > 3) return fail(nullptr, ADC_E_ARG, "adc_gemm: dtype must be 0..3");
+    if (M < 1 || N < 1 || K < 0) return fail(nullptr, ADC_E_ARG, "adc_gemm: M, N >= 1, K >= 0");
+    if (!A || !B || !C) return fail(nullptr, ADC_E_ARG, "adc_gemm: NULL operand");
+    if (lda < (ta ? M : K) || ldb < (tb ? K : N) || (!map && ldc < N))
+        return fail(nullptr, ADC_E_ARG, "adc_gemm: leading dimension too small");
+    if (config < -1 || config > 7) return fail(nullptr, ADC_E_ARG, "adc_gemm: config -1..7");
+    adc::GemmOut out = adc::GemmOut::rowmajor(ldc);
+    if (map) {
+        if (map[0] < 0 || map[3] < 0)
+            return fail(nullptr, ADC_E_ARG, "adc_gemm: bad output map");
+        out.rsplit = map[0];
+        out.rs1 = map[1];
+        out.rs2 = map[2];
+        out.csplit = map[3];
+        out.cs1 = map[4];
+        out.cs2 = map[5];
+    }
+    return guarded(nullptr, [&]() {
+        adc::Engine E;
+        E.stream = (hipStream_t)stream;
+        E.autotune = false;
+        E.force_cfg = config;
+        const bool a = ta != 0, b = tb != 0;
+        switch (dtype) {
+            case 0:
+                adc::gemm_run<double, double, double>(E, a, b, M, N, K, alpha, (const double*)A,
+                                                      lda, 0, (const double*)B, ldb, 0, beta,
+                                                      (double*)C, out, 1);
+                break;
+            case 1:
+                adc::gemm_run<float, float, float>(E, a, b, M, N, K, (float)alpha,
+                                                   (const float*)A, lda, 0, (const float*)B, ldb,
+                                                   0, (float)beta, (float*)C, out, 1);
+                break;
+            case 2:
+                adc::gemm_run<float, adc::bf16_t, float>(E, a, b, M, N, K, (float)alpha,
+                                                         (const float*)A, lda, 0, (const float*)B,
+                                                         ldb, 0, (float)beta, (float*)C, out, 1);
+                break;
+            default:
+                adc::gemm_run<adc::bf16_t, adc::bf16_t, float>(
+                    E, a, b, M, N, K, (float)alpha, (const adc::bf16_t*)A, lda, 0,
+                    (const adc::bf16_t*)B, ldb, 0, (float)beta, (float*)C, out, 1);
+        }
+        ADC_HIP(hipStreamSynchronize(E.stream));
+        return ADC_OK;
+    });
+}
+
 // ---- learned preconditioner -----------------------------------------------
 long long adc_mlp_nparams(void) { return adc::MLP_NPARAM; }
 
@@ -379,6 +449,64 @@ int adc_mlp_adam(adc_ctx* c, float* params, const float* grad, float* m, float* 
         ADC_HIP(hipStreamSynchronize(c->E.stream));
         return ADC_OK;
     });
+}
+
+}  // extern "C"
+
+struct adc_batch {
+    std::vector<adc_ctx*> ctx;
+};
+
+extern "C" {
+
+int adc_setup_batch(int nsys, const adc_system_desc* sys, adc_batch** out) {
+    if (!out) return fail(nullptr, ADC_E_ARG, "adc_setup_batch: out is NULL");
+    *out = nullptr;
+    if (nsys < 1 || !sys) return fail(nullptr, ADC_E_ARG, "adc_setup_batch: bad arguments");
+    adc_batch* b = new (std::nothrow) adc_batch;
+    if (!b) return fail(nullptr, ADC_E_OOM, "adc_setup_batch: host allocation failed");
+    for (int k = 0; k < nsys; ++k) {
+        adc_ctx* c = nullptr;
+        const adc_system_desc& d = sys[k];
+        int rc = adc_setup(d.eps, d.B, d.nocc, d.nvir, d.naux, d.order, d.kind, &c);
+        if (rc != ADC_OK) {
+            std::string msg = "adc_setup_batch: system " + std::to_string(k) + ": " + g_err;
+            adc_batch_destroy(b);
+            return fail(nullptr, rc, msg);
+        }
+        b->ctx.push_back(c);
+    }
+    *out = b;
+    return ADC_OK;
+}
+
+int adc_batch_set_option(adc_batch* b, const char* key, double value) {
+    if (!b) return fail(nullptr, ADC_E_ARG, "adc_batch_set_option: NULL batch");
+    for (size_t k = 0; k < b->ctx.size(); ++k) {
+        int rc = adc_set_option(b->ctx[k], key, value);
+        if (rc != ADC_OK)
+            return fail(nullptr, rc, "adc_batch_set_option: system " + std::to_string(k) + ": " +
+                                         b->ctx[k]->err);
+    }
+    return ADC_OK;
+}
+
+int adc_davidson_batch(adc_batch* b, int nroots, int flags, double* energies,
+                       double* spec_factors, int* n_iter, int* status, long long* stats) {
+    if (!b) return fail(nullptr, ADC_E_ARG, "adc_davidson_batch: NULL batch");
+    return adc_batch_davidson(b->ctx.data(), (int)b->ctx.size(), nroots, flags, energies,
+                              spec_factors, n_iter, status, stats);
+}
+
+adc_ctx* adc_batch_context(adc_batch* b, int k) {
+    if (!b || k < 0 || k >= (int)b->ctx.size()) return nullptr;
+    return b->ctx[k];
+}
+
+void adc_batch_destroy(adc_batch* b) {
+    if (!b) return;
+    for (adc_ctx* c : b->ctx) adc_destroy(c);
+    delete b;
 }
 
 int adc_batch_davidson(adc_ctx* const* ctxs, int nsys, int nroots, int flags,

@@ -389,6 +389,10 @@ struct Solver {
         }
         m = nb;
         newstart = 0;
+        if (m < nroots)
+            throw Error(ADC_E_NUMERIC, "initial Davidson space: " + std::to_string(m) +
+                                           " independent vectors for " + std::to_string(nroots) +
+                                           " roots (dependent guess vectors?)");
     }
 
     // sigma work of the coming iteration: the basis vectors without a sigma
@@ -467,8 +471,19 @@ struct Solver {
                                           d.S.p, m, d.th.p, d.ev_e.p, d.info.p));
             ADC_HIP(hipMemcpyAsync(theta.data(), d.th.p, m * sizeof(double),
                                    hipMemcpyDeviceToHost, E.stream));
+            int info = 0;
+            ADC_HIP(hipMemcpyAsync(&info, d.info.p, sizeof(int), hipMemcpyDeviceToHost,
+                                   E.stream));
+            ADC_HIP(hipStreamSynchronize(E.stream));
+            if (info != 0)
+                throw Error(ADC_E_NUMERIC, "projected eigenproblem: rocSOLVER did not converge "
+                                           "(info " + std::to_string(info) + ")");
         }
         nbk = std::min(block, m);
+        if (nbk < nroots)
+            throw Error(ADC_E_NUMERIC, "Davidson basis holds " + std::to_string(m) +
+                                           " independent vectors, fewer than the " +
+                                           std::to_string(nroots) + " roots asked for");
         // Ritz vectors: X = S^T V, AX = S^T W  (row k of S is eigenvector k)
         gemm_rm<double>(E, false, false, nbk, dim, m, 1.0, d.S.p, m, 0, d.V.p, dim, 0, 0.0, d.X.p,
                         dim, 0, 1);

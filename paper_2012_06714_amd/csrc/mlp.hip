@@ -238,9 +238,8 @@ static Work work(adc_ctx* c, long long n) {
     return w;
 }
 
-static void forward(adc_ctx* c, const float* P, const float* F, long long n, bool bf16,
+static void forward(Engine& E, const float* P, const float* F, long long n, bool bf16,
                     const Work& w, float* y) {
-    Engine& E = c->E;
     hipLaunchKernelGGL(k_layer1, dim3(nblocks(n * WD)), dim3(256), 0, E.stream, P, F, n, w.H1);
     ADC_HIP(hipGetLastError());
     // Z = H1 W2^T (W2 stored [out][in])
@@ -258,7 +257,7 @@ static void forward(adc_ctx* c, const float* P, const float* F, long long n, boo
 
 void mlp_forward(adc_ctx* c, const float* P, const float* F, long long n, bool bf16, float* y) {
     if (n <= 0) return;
-    forward(c, P, F, n, bf16, work(c, n), y);
+    forward(c->E, P, F, n, bf16, work(c, n), y);
 }
 
 // ---------------------------------------------------------------------------
@@ -319,7 +318,7 @@ double mlp_loss_grad(adc_ctx* c, const float* P, const float* F, const float* a,
     float* dy = (float*)E.scratch.get(45, sizeof(float) * n);
     float* ones = (float*)E.scratch.get(46, sizeof(float) * n);
     fill<float>(E, ones, 1.f, (size_t)n);
-    forward(c, P, F, n, false, w, y);
+    forward(c->E, P, F, n, false, w, y);
     const unsigned nb = (unsigned)std::min<long long>(1024, (n + 255) / 256);
     double* part = (double*)E.scratch.get(47, sizeof(double) * nb);
     hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, E.stream, y, a, t, n, dy, part);
@@ -429,7 +428,7 @@ bool mlp_precondition(adc_ctx* c, const double* R, const std::vector<double>& th
             hipLaunchKernelGGL(k_features, dim3(nblocks(n)), dim3(256), 0, E.stream, r,
                                c->diag.p, theta[sel[k]], inv_rms, e0, n, o, F);
             ADC_HIP(hipGetLastError());
-            forward(c, c->mlp_params.p, F, n, true, w, y);
+            forward(c->E, c->mlp_params.p, F, n, true, w, y);
             hipLaunchKernelGGL(k_combine, dim3(nblocks(n)), dim3(256), 0, E.stream, r, c->diag.p,
                                y, theta[sel[k]], inv_rms, e0, n, Dout + (size_t)k * dim, bad);
             ADC_HIP(hipGetLastError());

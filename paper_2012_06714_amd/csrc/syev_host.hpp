@@ -16,8 +16,10 @@ namespace adc {
 // A: n x n symmetric, row-major (only read).  On success w[k] holds the
 // eigenvalues in ascending order and row k of S (n x n, row-major) the unit
 // eigenvector of w[k]; the lowest nref eigenvalues are recomputed as Rayleigh
-// quotients of their vectors.  Returns false when the QR sweeps do not converge.
-inline bool syev_host(int n, const double* A, double* w, double* S, int nref = 0) {
+// quotients of their vectors.  Returns false when the QR sweeps do not converge
+// within max_sweeps (default 60 n) implicit QR steps.
+inline bool syev_host(int n, const double* A, double* w, double* S, int nref = 0,
+                      long long max_sweeps = -1) {
     if (n <= 0) return true;
     // Zt holds the accumulated transformation transposed (row k = column k),
     // so that rotations and reflections touch contiguous rows
@@ -74,14 +76,16 @@ inline bool syev_host(int n, const double* A, double* w, double* S, int nref = 0
     for (int i = 0; i + 1 < n; ++i) e[i] = a[(size_t)(i + 1) * n + i];
     // ---- implicit QR on the unreduced trailing block [lo, hi]
     const double eps = DBL_EPSILON;
-    int hi = n - 1, sweeps = 0;
+    int hi = n - 1;
+    long long sweeps = 0;
+    if (max_sweeps < 0) max_sweeps = 60LL * n;
     while (hi > 0) {
         if (std::fabs(e[hi - 1]) <= eps * (std::fabs(d[hi - 1]) + std::fabs(d[hi]))) {
             e[hi - 1] = 0.0;
             --hi;
             continue;
         }
-        if (++sweeps > 60 * n) return false;
+        if (++sweeps > max_sweeps) return false;
         int lo = hi - 1;
         while (lo > 0 && std::fabs(e[lo - 1]) > eps * (std::fabs(d[lo - 1]) + std::fabs(d[lo])))
             --lo;

@@ -93,6 +93,11 @@ void gemm_run(Engine& E, bool ta, bool tb, long long M, long long N, long long K
     const std::array<long long, 12> key{(long long)sizeof(TI), (long long)sizeof(T),
                                         (long long)sizeof(TO), ta, tb, M, N, K, batch * inner.n,
                                         kind, out.rsplit > 0, out.csplit > 0};
+    if (E.force_cfg >= 0) {   // a forced tile (configurations not compiled for T run as 0)
+        mfma_gemm<TI, T, TO>(E.stream, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,
+                             out, batch, kind, E.force_cfg, inner);
+        return;
+    }
     auto it = E.tuned.find(key);
     if (it != E.tuned.end()) {
         mfma_gemm<TI, T, TO>(E.stream, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,

@@ -49,3 +49,15 @@ def test_host_validation_without_gpu():
     assert lib.adc_batch_davidson(arr, 1, 1, 4, e, None, None, None, None) == adc.ADC_E_ARG
     assert lib.adc_batch_davidson(arr, 1, 1, 2 | (65 << 8), e, None, None, None, None) == adc.ADC_E_ARG
     lib.adc_destroy(None)
+    # the batch object: argument checks before any device work
+    assert lib.adc_setup_batch(1, None, ctypes.byref(h)) == adc.ADC_E_ARG
+    assert lib.adc_setup_batch(0, dummy, ctypes.byref(h)) == adc.ADC_E_ARG
+    assert lib.adc_setup_batch(1, dummy, None) == adc.ADC_E_ARG
+    desc = adc._SystemDesc(None, 8, 2, 3, 4, 2, 1)
+    assert lib.adc_setup_batch(1, ctypes.byref(desc), ctypes.byref(h)) == adc.ADC_E_ARG
+    assert "system 0" in adc.last_error() and "NULL" in adc.last_error()
+    assert h.value is None
+    assert lib.adc_davidson_batch(None, 1, 0, e, None, None, None, None) == adc.ADC_E_ARG
+    assert lib.adc_batch_set_option(None, b"tol_e", 1e-8) == adc.ADC_E_ARG
+    assert lib.adc_batch_context(None, 0) is None
+    lib.adc_batch_destroy(None)

@@ -1,7 +1,10 @@
 """sigma replayed from captured HIP graphs (option "graph") against the eager
-calls of the same library: identical kernels in identical order, so the
+calls of the same library (identical kernels in identical order, so the
 results must agree bit for bit, on every replay, with eager work and other
-graph shapes interleaved."""
+graph shapes interleaved) and against the CPU oracle (FP64: to 1e-11 of the
+oracle's magnitude of the same sums, element by element; BF16 products: to
+3e-2 of it); the graph-replayed Davidson solve against the oracle's
+eigenpairs."""
 import sys
 
 import numpy as np
@@ -34,16 +37,22 @@ def test_graph_sigma_replays_match_eager(order, kind, precision):
     for c in (eager, graph):
         c.set_option("precision", precision)
     graph.set_option("graph", 1)
+    from oracle.radc import RADC
+    orc = RADC(eps, B, O, order, kind)
+    tol = 1e-11 if precision == 0 else 3e-2
     dim = eager.dim
     for rep in range(4):
         nvec = 5 if rep % 2 == 0 else 3
-        X = torch.tensor(random_vectors(dim, nvec, 100 + rep), device="cuda")
+        Xh = random_vectors(dim, nvec, 100 + rep)
+        X = torch.tensor(Xh, device="cuda")
         ref = eager.sigma(X)
         out = graph.sigma(X)
         d = graph.diag()                 # eager work between replays
         torch.cuda.synchronize()
         assert torch.equal(out, ref), f"replay {rep}"
         assert torch.isfinite(d).all()
+        err = np.abs(out.cpu().numpy() - orc.sigma(Xh)) / (orc.sigma_magnitude(Xh) + 1e-300)
+        assert err.max() <= tol, f"replay {rep} vs oracle: {err.max():.3e}"
     assert graph.graph_launches() == 4
     eager.close()
     graph.close()
@@ -62,3 +71,12 @@ def test_graph_davidson_matches_eager():
     c.close()
     assert ok0 and ok1 and n >= it1
     assert np.abs(np.array(e1) - np.array(e0)).max() < 1e-9
+    # the oracle's own solve (sigma and Davidson of the oracle package)
+    from oracle.davidson import davidson
+    from oracle.radc import RADC
+    orc = RADC(eps, B, 4, 3, "ea")
+    w, vec, _, conv = davidson(orc.sigma, orc.diag(), 3, block=6, tol_e=1e-11, tol_r=1e-8)
+    assert conv
+    P_ref = orc.spec_factors(vec)
+    assert np.abs(np.array(e1) - w).max() < 1e-8
+    assert (np.abs(np.array(P1) - P_ref) / np.maximum(1, np.abs(P_ref))).max() < 1e-5

@@ -145,3 +145,72 @@ def test_davidson_matches_dense_ip_adc2_o5v19():
     P_ref = r.spec_factors(v[:, :4].T)
     # eigenvector error ~ ||r|| / gap = 1e-6 scale; the benchmark spec's bound on P is 1e-5
     assert np.abs(r.spec_factors(X) - P_ref).max() < 1e-5
+
+
+@pytest.mark.parametrize("kind", ["ea", "ip"])
+@pytest.mark.parametrize("order", [2, 3])
+def test_sliced_einsum_branch_matches_whole_terms(monkeypatch, kind, order):
+    """The oracle evaluates a term whose einsum intermediate exceeds
+    EINSUM_LIMIT elements slice by slice along an output index (the large
+    systems take that branch).  With the limit forced tiny every term of these
+    small systems is sliced, several levels deep: the explicit matrix, sigma,
+    the diagonal, the spectroscopic factors and the amplitudes must equal the
+    whole-term evaluation, which the Fock-space pins above fix."""
+    import oracle.radc as radc_mod
+    eps, B = small_system(2, 4, 9, 17)
+    ref = RADC(eps, B, 2, order, kind)
+    M_ref = ref.explicit()
+    w, v = np.linalg.eigh(M_ref)
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((3, ref.dim))
+    S_ref = ref.sigma(X)
+    P_ref = ref.spec_factors(v[:, :3].T)
+    D_ref = ref.diag()
+    calls = {"n": 0}
+    orig = radc_mod._einsum_sliced
+
+    def counting(subs, out, ops):
+        calls["n"] += 1
+        return orig(subs, out, ops)
+
+    monkeypatch.setattr(radc_mod, "EINSUM_LIMIT", 24.0)
+    monkeypatch.setattr(radc_mod, "_einsum_sliced", counting)
+    r = RADC(eps, B, 2, order, kind)
+    for name in ("t", "s", "u", "w"):
+        if name in ref.T:
+            a, b = ref.T[name], r.T[name]
+            assert np.abs(a - b).max() <= 1e-14 * max(1.0, np.abs(a).max())
+    M = r.explicit()
+    scale = np.abs(M_ref).max()
+    assert np.abs(M - M_ref).max() <= 1e-13 * scale
+    assert np.abs(r.sigma(X) - S_ref).max() <= 1e-13 * np.abs(S_ref).max()
+    assert np.abs(r.diag() - D_ref).max() <= 1e-13 * scale
+    assert np.abs(r.spec_factors(v[:, :3].T) - P_ref).max() <= 1e-12 * max(1.0, np.abs(P_ref).max())
+    # the branch really ran: sliced calls recurse, so there are more calls than terms
+    n_whole = calls["n"]
+    calls["n"] = 0
+    monkeypatch.setattr(radc_mod, "EINSUM_LIMIT", 2.0e8)
+    RADC(eps, B, 2, order, kind).sigma(X)
+    assert n_whole > 2 * calls["n"] > 0
+
+
+@pytest.mark.parametrize("kind", ["ea", "ip"])
+@pytest.mark.parametrize("order", [2, 3])
+def test_sigma_magnitude_bounds_every_product(kind, order):
+    """The error scale used for reduced-precision sigma comparisons bounds
+    |sigma| element by element (triangle inequality), depends only on |X|,
+    is linear in |X|, and equals |M_Z| |X| when every product is a single
+    nonnegative term (here checked against brute force: the explicit matrix's
+    absolute values never exceed the magnitude of the unit vectors)."""
+    eps, B = small_system(2, 3, 8, 4)
+    r = RADC(eps, B, 2, order, kind)
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((4, r.dim))
+    S, A = r.sigma(X), r.sigma_magnitude(X)
+    assert np.all(A >= np.abs(S) - 1e-12 * np.abs(A).max())
+    assert np.allclose(r.sigma_magnitude(np.abs(X)), A, rtol=1e-13, atol=0)
+    assert np.allclose(r.sigma_magnitude(2.5 * X), 2.5 * A, rtol=1e-13, atol=0)
+    Mabs = r.sigma_magnitude(np.eye(r.dim)).T
+    M = r.explicit()
+    assert np.all(Mabs >= np.abs(M) - 1e-12 * np.abs(Mabs).max())
+    assert np.all(A <= (np.abs(X) @ Mabs.T) * (1 + 1e-12) + 1e-12)

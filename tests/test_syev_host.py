@@ -13,12 +13,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 DRIVER = r"""
 #include "syev_host.hpp"
 #include <cstdio>
-int main() {
+#include <cstdlib>
+int main(int argc, char** argv) {
+    const long long cap = argc > 1 ? std::atoll(argv[1]) : -1;
     int n;
     while (std::scanf("%d", &n) == 1) {
         std::vector<double> A((size_t)n * n), w(n), S((size_t)n * n);
         for (auto& x : A) if (std::scanf("%lf", &x) != 1) return 2;
-        if (!adc::syev_host(n, A.data(), w.data(), S.data(), n)) { std::printf("FAIL\n"); continue; }
+        if (!adc::syev_host(n, A.data(), w.data(), S.data(), n, cap)) { std::printf("FAIL\n"); continue; }
         for (double x : w) std::printf("%.17g\n", x);
         for (double x : S) std::printf("%.17g\n", x);
     }
@@ -74,3 +76,20 @@ def test_host_eigensolver_matches_lapack(solver):
         assert np.abs(S @ S.T - np.eye(n)).max() <= 1e-13 * n
         assert np.abs(a @ S.T - S.T * w).max() <= 1e-13 * n * scale
     assert pos == len(vals)
+
+
+def test_host_eigensolver_reports_unconverged_sweeps(solver):
+    """With the QR sweep budget set to 0 a matrix that is not already diagonal
+    cannot converge: the solver must say so (the Davidson driver then hands
+    the projected problem to rocSOLVER), while a diagonal one needs no sweep."""
+    rng = np.random.default_rng(9)
+    a = rng.standard_normal((6, 6))
+    a = a + a.T
+    d = np.diag([3.0, 1.0, 2.0])
+    text = "".join(f"{m.shape[0]}\n" + " ".join(f"{x:.17g}" for x in m.ravel()) + "\n"
+                   for m in (a, d))
+    res = subprocess.run([solver, "0"], input=text, capture_output=True, text=True, check=True)
+    vals = res.stdout.split()
+    assert vals[0] == "FAIL"
+    w = np.array(vals[1:4], dtype=float)
+    assert np.array_equal(w, [1.0, 2.0, 3.0])
