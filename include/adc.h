@@ -348,6 +348,22 @@ int adc_mlp_pairs(adc_ctx* ctx, const double* x, const double* r, double theta,
 int adc_mlp_forward(adc_ctx* ctx, const float* params, const float* F, long long n, int bf16,
                     float* y);
 
+/* adc_mlp_forward for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): no context, no allocation.  The hidden activations of the
+ * network live in a static device array the library holds on each GPU it
+ * runs on until the process ends (8192 rows x 3 x 256 FP32 = 24 MiB); the
+ * first call on a device looks its address up (not a stream operation, but
+ * make that first call outside a capture).  params: device
+ * [adc_mlp_nparams()] FP32; F: device [n][7] FP32; y: device [n] FP32
+ * (written); all caller-owned.  bf16 as in adc_mlp_forward.  The work is
+ * enqueued on `stream` (hipStream_t, NULL: the null stream) and the call
+ * returns without synchronising.  1 <= n <= 8192, else ADC_E_ARG; ADC_E_HIP
+ * on a launch failure (messages in adc_last_error(NULL)).  Calls that
+ * overlap on one GPU (other streams or threads) share the array and race. */
+int adc_mlp_forward_noalloc(const float* params, const float* F, long long n, int bf16, float* y,
+                            void* stream);
+
 /* loss = 0.5 mean_e (a_e (1 + y_e) - t_e)^2 over n pairs (host output) and
  * its gradient grad[adc_mlp_nparams()] (device) with respect to params,
  * FP32 forward and backward. */

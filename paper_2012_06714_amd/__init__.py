@@ -26,7 +26,7 @@ ABI_SYMBOLS = ("adc_setup", "adc_set_option", "adc_set_stream", "adc_dim", "adc_
                "adc_mlp_adam", "adc_record_count", "adc_record_get", "adc_graph_launches",
                "adc_batch_davidson", "adc_setup_batch", "adc_batch_set_option",
                "adc_davidson_batch", "adc_batch_context", "adc_batch_destroy", "adc_gemm",
-               "adc_gemm_configs")
+               "adc_gemm_configs", "adc_mlp_forward_noalloc")
 
 
 class ADCError(RuntimeError):
@@ -75,6 +75,7 @@ def _load():
         "adc_batch_destroy": (None, [vp]),
         "adc_gemm": (i, [i, i, i, ll, ll, ll, d, vp, ll, vp, ll, d, vp, ll, vp, i, vp]),
         "adc_gemm_configs": (i, [i, vp]),
+        "adc_mlp_forward_noalloc": (i, [vp, vp, ll, i, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -150,6 +151,21 @@ def gemm(dtype, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, omap=None,
                         _dev(A, torch, st[0]), int(lda), _dev(B, torch, st[0]), int(ldb),
                         float(beta), _dev(C, torch, st[1]), int(ldc), m, int(config),
                         ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+
+MLP_NOALLOC_ROWS = 8192
+
+
+def mlp_forward_noalloc(params, F, y, bf16=False, stream=None):
+    """adc_mlp_forward_noalloc: y[n] (float32 device, written) for features
+    F [n, 7] (float32 device), no allocation anywhere; enqueued on `stream`
+    (default: torch's current stream) without synchronising."""
+    import torch
+    f32 = torch.float32
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib.adc_mlp_forward_noalloc(_dev(params, torch, f32), _dev(F, torch, f32),
+                                       int(F.shape[0]), int(bool(bf16)), _dev(y, torch, f32),
+                                       ctypes.c_void_p(st.cuda_stream)))
 
 
 class _SystemDesc(ctypes.Structure):

@@ -416,6 +416,19 @@ int adc_mlp_pairs(adc_ctx* c, const double* x, const double* r, double theta, co
     });
 }
 
+int adc_mlp_forward_noalloc(const float* params, const float* F, long long n, int bf16, float* y,
+                            void* stream) {
+    if (!params || !F || !y) return fail(nullptr, ADC_E_ARG, "adc_mlp_forward_noalloc: NULL pointer");
+    if (n < 1 || n > adc::MLP_NOALLOC_ROWS)
+        return fail(nullptr, ADC_E_ARG,
+                    "adc_mlp_forward_noalloc: n must be 1.." + std::to_string(adc::MLP_NOALLOC_ROWS));
+    return guarded(nullptr, [&]() {
+        adc::mlp_forward_noalloc(params, F, n, bf16 != 0, y, (hipStream_t)stream);
+        ADC_HIP(hipGetLastError());
+        return ADC_OK;
+    });
+}
+
 int adc_mlp_forward(adc_ctx* c, const float* params, const float* F, long long n, int bf16,
                     float* y) {
     if (!c) return fail(nullptr, ADC_E_ARG, "adc_mlp_forward: NULL context");

@@ -153,6 +153,9 @@ constexpr long long MLP_NPARAM = MLP_WIDTH * MLP_NF + MLP_WIDTH + MLP_WIDTH * ML
 void mlp_pairs(adc_ctx* c, const double* x, const double* r, double theta, const double* xstar,
                const long long* idx, long long nidx, float* F, float* a, float* t);
 void mlp_forward(adc_ctx* c, const float* P, const float* F, long long n, bool bf16, float* y);
+constexpr long long MLP_NOALLOC_ROWS = 8192;   // rows of one no-allocation inference call
+void mlp_forward_noalloc(const float* P, const float* F, long long n, bool bf16, float* y,
+                         hipStream_t stream);
 double mlp_loss_grad(adc_ctx* c, const float* P, const float* F, const float* a, const float* t,
                      long long n, float* G);
 void mlp_adam(adc_ctx* c, float* P, const float* G, float* m, float* v, long long np, int step,

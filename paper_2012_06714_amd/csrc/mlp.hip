@@ -20,6 +20,9 @@
 #include "context.hpp"
 
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <string>
 
 namespace adc {
 
@@ -258,6 +261,44 @@ static void forward(Engine& E, const float* P, const float* F, long long n, bool
 void mlp_forward(adc_ctx* c, const float* P, const float* F, long long n, bool bf16, float* y) {
     if (n <= 0) return;
     forward(c->E, P, F, n, bf16, work(c, n), y);
+}
+
+// ---------------------------------------------------------------------------
+// inference without allocation
+// ---------------------------------------------------------------------------
+// The hidden activations H1, Z, H2 of up to MLP_NOALLOC_ROWS rows live in this
+// file-scope device array (each GPU holds its own copy until the process
+// ends).  Its name is only a host-side stand-in: host code uses the address
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device on the first call there.  Every row of the three activations is
+// written before it is read, so nothing needs clearing between calls; calls
+// that overlap on one GPU share the array and race.
+static __device__ __align__(256) float scratch[MLP_NOALLOC_ROWS * 3 * WD];
+
+static float* noalloc_scratch() {
+    static std::mutex mu;
+    static std::map<int, float*> ptr;
+    int dev = 0;
+    ADC_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = ptr.find(dev);
+    if (it != ptr.end()) return it->second;
+    void* p = nullptr;
+    ADC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    ptr[dev] = static_cast<float*>(p);
+    return static_cast<float*>(p);
+}
+
+void mlp_forward_noalloc(const float* P, const float* F, long long n, bool bf16, float* y,
+                         hipStream_t stream) {
+    ADC_REQUIRE(n >= 1 && n <= MLP_NOALLOC_ROWS,
+                "adc_mlp_forward_noalloc: n must be 1.." + std::to_string(MLP_NOALLOC_ROWS));
+    float* s = noalloc_scratch();
+    Engine E;              // stream only: no autotuner trials (they would create events),
+    E.stream = stream;     // and the 256-long sums never take the split-K path
+    E.autotune = false;
+    const Work w{s, s + 2 * MLP_NOALLOC_ROWS * WD, s + MLP_NOALLOC_ROWS * WD};   // H1, H2, Z
+    forward(E, P, F, n, bf16, w, y);
 }
 
 // ---------------------------------------------------------------------------
