@@ -69,8 +69,10 @@ enum {
     ADC_E_NOCONV = 1     /* solver stopped at max_iter; outputs are estimates */
 };
 
-/* Steps 1-3 of Sec. III.A.  Stages eps (device, [N]) and B (device,
- * [Q][N][N]) into the library's layouts, computes the MP amplitudes
+/* Steps 1-3 of Sec. III.A.  Stages eps ([N]) and B ([Q][N][N]), each either
+ * device memory or host memory (host B is copied in blocks of auxiliary
+ * functions, so the caller's B need not occupy the GPU), into the library's
+ * layouts, computes the MP amplitudes
  * (t2 first order; for order 3 also the second-order singles and doubles
  * and third-order singles, Eqs. 13-14) and the 1p-1p (EA) or 1h-1h (IP)
  * block through order `order`, and keeps everything resident on the device.
@@ -81,6 +83,19 @@ enum {
 int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
               int order, int kind, adc_ctx** out);
 
+/* Options taken by later adc_setup calls of the calling thread (the setup
+ * runs before any adc_set_option can reach the context):
+ *   "slice_budget"  elements per operand slice of the setup's large
+ *                   contractions (four-index products are evaluated in slices
+ *                   of this size or less, so that the setup's temporaries stay
+ *                   bounded; default 0 = 2^28); results do not depend on it
+ *                   beyond the order of floating-point sums;
+ *   "verbose"       1: one line on stderr per setup phase and per block of
+ *                   its long loops, with the seconds since adc_setup began
+ *                   (each line synchronises the stream); 0 (default): silent.
+ * Errors: ADC_E_ARG for an unknown key or a bad value. */
+int adc_set_setup_option(const char* key, double value);
+
 /* Options (numeric values):
  *   "precision"   0 = FP64 sigma (default); 1 = mixed: sigma contractions
  *                 with BF16 products and FP32 sums (FP32 storage), FP64
@@ -90,7 +105,9 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
  *                 (2: FP32 products)
  *   "block"       trial vectors per sigma launch in adc_davidson (default:
  *                 max(nroots, 8))
- *   "max_space"   Davidson subspace limit (default 8 * block)
+ *   "max_space"   Davidson subspace limit (default 8 * block, lowered to what
+ *                 fits in a quarter of the free device memory, but at least
+ *                 3 * block)
  *   "max_iter"    Davidson iteration limit (default 300)
  *   "tol_e"       eigenvalue change tolerance in Eh (default 1e-8)
  *   "tol_r"       residual norm tolerance, in units of max(1, |theta|) for
@@ -125,9 +142,14 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
  *                 O^2 V^2 FP64 tensors, seven BF16 ones in the mixed mode,
  *                 and two O V Naux matrices that fold t~ into the coupling)
  *                 so that each large contraction is one matrix-core product,
- *                 0 = generic contractions (permute per call), -1 = 1 when
- *                 the extra tensors fit in half of the free device memory
- *                 (default)
+ *                 0 = generic contractions (permute per call), 2 = the same
+ *                 products as 1 with each product-ready operand built per
+ *                 call, one block of its leading index at a time, from the
+ *                 resident t, (ov|ov) and (oo|vv) (for systems whose extra
+ *                 tensors do not fit: t~ is then released and t~ + u~ of the
+ *                 spectroscopic amplitudes kept in pinned host memory), -1 = 1
+ *                 when the extra tensors fit in half of the free device
+ *                 memory, else 2 (default)
  *   "ctr_log"     1 = time each generic contraction with HIP events and
  *                 print its product shape on stderr (sigma then runs eagerly)
  *   "gemm_config" -1 = tile configuration of each matrix-core product chosen
@@ -179,6 +201,27 @@ int adc_davidson(adc_ctx* ctx, int nroots, double* energies, double* spec_factor
  * P: host [nvec].  X (optional, device [nvec][N], may be NULL) receives
  * the spectroscopic amplitudes X_p (occupied orbitals first). */
 int adc_spec_factors(adc_ctx* ctx, const double* vecs, int nvec, double* P, double* X);
+
+/* Spectra from the solver's outputs (no context; device pointers on
+ * `stream`, a hipStream_t or NULL; caller-owned; synchronises the stream).
+ * adc_spectral_function: the density of states / photoelectron spectrum of
+ * Sec. IV (the ADC density of states of Sec. II with broadening eta):
+ *   A[k] = -(1/pi) Im sum_mu P[mu] / (omega[k] - energies[mu] + i eta)
+ *        = (1/pi) sum_mu P[mu] eta / ((omega[k] - energies[mu])^2 + eta^2)
+ * omega [nomega], energies and P [nroots] (for example adc_davidson's outputs
+ * copied to the device), A [nomega] (written).  With P from Eq. 50 (both spin
+ * components) this is -(1/pi) Im of the trace of G over spin orbitals.
+ * adc_propagator_diag: the diagonal of the ADC propagator of Sec. II,
+ *   G_pp(omega[k] + i eta) = sum_mu X[mu][p]^2 / (omega[k] - energies[mu] + i eta)
+ * for the spectroscopic amplitudes X [nroots][norb] of adc_spec_factors (one
+ * spin component; these amplitudes are also the coefficients of the Dyson
+ * orbitals of Sec. IV in the reference orbitals), written to
+ * G [nomega][norb][2] as (real, imaginary).
+ * Errors: ADC_E_ARG (NULL pointer, sizes < 1, eta <= 0), ADC_E_HIP. */
+int adc_spectral_function(const double* omega, int nomega, const double* energies, const double* P,
+                          int nroots, double eta, double* A, void* stream);
+int adc_propagator_diag(const double* omega, int nomega, const double* energies, const double* X,
+                        int nroots, int norb, double eta, double* G, void* stream);
 
 /* Warm start: the next adc_davidson starts from these nvec vectors
  * (device [nvec][dim], copied). */

@@ -26,7 +26,8 @@ ABI_SYMBOLS = ("adc_setup", "adc_set_option", "adc_set_stream", "adc_dim", "adc_
                "adc_mlp_adam", "adc_record_count", "adc_record_get", "adc_graph_launches",
                "adc_batch_davidson", "adc_setup_batch", "adc_batch_set_option",
                "adc_davidson_batch", "adc_batch_context", "adc_batch_destroy", "adc_gemm",
-               "adc_gemm_configs", "adc_mlp_forward_noalloc")
+               "adc_gemm_configs", "adc_mlp_forward_noalloc", "adc_set_setup_option",
+               "adc_spectral_function", "adc_propagator_diag")
 
 
 class ADCError(RuntimeError):
@@ -76,6 +77,9 @@ def _load():
         "adc_gemm": (i, [i, i, i, ll, ll, ll, d, vp, ll, vp, ll, d, vp, ll, vp, i, vp]),
         "adc_gemm_configs": (i, [i, vp]),
         "adc_mlp_forward_noalloc": (i, [vp, vp, ll, i, vp, vp]),
+        "adc_set_setup_option": (i, [ctypes.c_char_p, d]),
+        "adc_spectral_function": (i, [vp, i, vp, vp, i, d, vp, vp]),
+        "adc_propagator_diag": (i, [vp, i, vp, vp, i, i, d, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -102,6 +106,21 @@ def _dev(x, torch, dtype=None):
     if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == dtype and x.is_contiguous()):
         raise TypeError("expected a contiguous CUDA tensor of dtype %s" % dtype)
     return ctypes.c_void_p(x.data_ptr())
+
+
+def _dev_or_host(x, torch):
+    """A float64 input adc_setup accepts in device or host memory: a contiguous
+    CUDA tensor, a contiguous CPU tensor or a C-contiguous numpy array."""
+    import numpy as np
+    if isinstance(x, np.ndarray):
+        if x.dtype != np.float64 or not x.flags["C_CONTIGUOUS"]:
+            raise TypeError("expected a C-contiguous float64 array")
+        return ctypes.c_void_p(x.ctypes.data)
+    if isinstance(x, torch.Tensor) and not x.is_cuda:
+        if x.dtype != torch.float64 or not x.is_contiguous():
+            raise TypeError("expected a contiguous float64 tensor")
+        return ctypes.c_void_p(x.data_ptr())
+    return _dev(x, torch)
 
 
 def batch_davidson(contexts, nroots, use_graph=True, concurrent=False, threads=0):
@@ -154,6 +173,34 @@ def gemm(dtype, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, omap=None,
 
 
 MLP_NOALLOC_ROWS = 8192
+
+
+def spectral_function(omega, energies, P, eta):
+    """adc_spectral_function on float64 CUDA tensors: A(omega) [nomega]."""
+    import torch
+    A = torch.empty_like(omega)
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _check(lib.adc_spectral_function(_dev(omega, torch), omega.numel(), _dev(energies, torch),
+                                     _dev(P, torch), energies.numel(), float(eta), _dev(A, torch),
+                                     st))
+    return A
+
+
+def propagator_diag(omega, energies, X, eta):
+    """adc_propagator_diag: complex [nomega, norb] tensor G_pp(omega + i eta)."""
+    import torch
+    nr, norb = X.shape
+    G = torch.empty((omega.numel(), norb, 2), dtype=torch.float64, device=omega.device)
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _check(lib.adc_propagator_diag(_dev(omega, torch), omega.numel(), _dev(energies, torch),
+                                   _dev(X.contiguous(), torch), nr, norb, float(eta),
+                                   _dev(G, torch), st))
+    return torch.complex(G[..., 0], G[..., 1])
+
+
+def set_setup_option(key, value):
+    """adc_set_setup_option: an option for later adc_setup calls of this thread."""
+    _check(lib.adc_set_setup_option(key.encode(), float(value)))
 
 
 def mlp_forward_noalloc(params, F, y, bf16=False, stream=None):
@@ -235,7 +282,8 @@ class Batch:
 class Context:
     """One ADC(n) problem resident on the current GPU.
 
-    eps: [N] float64 CUDA tensor; B: [Naux, N, N] float64 CUDA tensor.
+    eps: [N], B: [Naux, N, N], float64: CUDA tensors, or host memory (CPU
+    tensors or numpy arrays; B is then staged in blocks).
     kind: "ea" or "ip"; order: 2 or 3.
     """
 
@@ -248,8 +296,8 @@ class Context:
         self.order, self.kind = int(order), kind
         h = ctypes.c_void_p()
         k = ADC_EA if kind == "ea" else ADC_IP if kind == "ip" else -9
-        rc = lib.adc_setup(_dev(eps, torch), _dev(B, torch), self.nocc, self.nvir, self.naux,
-                           self.order, k, ctypes.byref(h))
+        rc = lib.adc_setup(_dev_or_host(eps, torch), _dev_or_host(B, torch), self.nocc,
+                           self.nvir, self.naux, self.order, k, ctypes.byref(h))
         _check(rc)
         self._h = h
         self.dim = int(lib.adc_dim(h))

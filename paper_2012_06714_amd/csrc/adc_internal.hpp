@@ -167,12 +167,28 @@ struct Engine {
     bool timing = false;     // record events around the particle-particle kernels
     bool ctr_log = false;    // time every contraction and print its GEMM plan to stderr
     int force_cfg = -1;      // GEMM tile configuration forced on every product (-1: automatic)
+    long long slice_budget = 1LL << 28;   // elements per operand view of ctr_sliced
     double pp_ms = 0.0;      // accumulated milliseconds of those kernels
 };
 
 template <typename T>
 void ctr(Engine& E, T alpha, const char* sa, const T* A, const char* sb, const T* B, T beta,
          const char* sc, T* C);
+
+// The same contraction restricted to slices: every letter of `sl` takes the
+// values [lo, lo + n) in every operand that carries it (a summed letter sums
+// over that range only).  Operands are full tensors with the engine's extents;
+// a view that is not contiguous is gathered into scratch, a non-contiguous
+// output slice computed in scratch and scattered back.  Views larger than
+// `budget` elements (<= 0: the engine's slice_budget) are split further along
+// their longest axis, so no temporary exceeds the budget.
+struct Slice {
+    char c;
+    long long lo, n;
+};
+template <typename T>
+void ctr_sliced(Engine& E, T alpha, const char* sa, const T* A, const char* sb, const T* B, T beta,
+                const char* sc, T* C, const std::vector<Slice>& sl = {}, long long budget = 0);
 
 // Permute-accumulate: out[so] = beta*out + alpha*in[si]  (same letters).
 template <typename T>

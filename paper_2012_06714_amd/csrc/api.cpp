@@ -11,6 +11,9 @@
 namespace {
 
 thread_local std::string g_err = "no error";
+// setup options of this thread (adc_set_setup_option), applied by adc_setup
+thread_local long long g_slice_budget = 0;
+thread_local int g_setup_verbose = 0;
 
 int fail(adc_ctx* c, int code, const std::string& msg) {
     if (c)
@@ -68,6 +71,9 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux, 
     }
     c->dim = c->n1 + c->n2x * c->n2p * c->n2p;
     c->E.scratch.arena = &c->arena;
+    if (g_slice_budget > 0) c->E.slice_budget = g_slice_budget;
+    c->setup_verbose = g_setup_verbose;
+    c->setup_t0 = std::chrono::steady_clock::now();
     int rc = guarded(nullptr, [&]() {
         ADC_BLAS(rocblas_create_handle(&c->E.blas));
         c->own_blas = true;
@@ -81,6 +87,23 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux, 
     }
     *out = c;
     return ADC_OK;
+}
+
+int adc_set_setup_option(const char* key, double value) {
+    if (!key) return fail(nullptr, ADC_E_ARG, "adc_set_setup_option: NULL key");
+    std::string k(key);
+    if (k == "slice_budget") {
+        if (!(value >= 0) || value > 1e15 || value != std::floor(value))
+            return fail(nullptr, ADC_E_ARG, "slice_budget: a count of elements >= 0");
+        g_slice_budget = (long long)value;
+        return ADC_OK;
+    }
+    if (k == "verbose") {
+        if (value != 0 && value != 1) return fail(nullptr, ADC_E_ARG, "verbose: 0 or 1");
+        g_setup_verbose = (int)value;
+        return ADC_OK;
+    }
+    return fail(nullptr, ADC_E_ARG, "adc_set_setup_option: unknown key '" + k + "'");
 }
 
 int adc_set_option(adc_ctx* c, const char* key, double value) {
@@ -146,9 +169,10 @@ int adc_set_option(adc_ctx* c, const char* key, double value) {
         c->pp_group = (int)value;
         adc::drop_graphs(c);
     } else if (k == "ea_layout") {
-        // EA sigma: -1 arranged operands when they fit in memory, 0 generic
-        // contractions, 1 arranged operands
-        if (value != -1 && value != 0 && value != 1) return fail(c, ADC_E_ARG, "ea_layout: -1, 0 or 1");
+        // EA sigma: -1 arranged operands when they fit in memory, else built in
+        // blocks per call; 0 generic contractions; 1 arranged; 2 blocked
+        if (value != -1 && value != 0 && value != 1 && value != 2)
+            return fail(c, ADC_E_ARG, "ea_layout: -1, 0, 1 or 2");
         c->ea_layout = (int)value;
         adc::drop_graphs(c);
     } else if (k == "ctr_log") {
@@ -307,6 +331,33 @@ int adc_sigma_timed(adc_ctx* c, const double* X, double* Y, int nvec, double* ms
         if (ms_pp) *ms_pp = c->E.pp_ms;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        return ADC_OK;
+    });
+}
+
+// ---- spectra from the solver's outputs -------------------------------------
+int adc_spectral_function(const double* omega, int nomega, const double* energies, const double* P,
+                          int nroots, double eta, double* A, void* stream) {
+    if (!omega || !energies || !P || !A)
+        return fail(nullptr, ADC_E_ARG, "adc_spectral_function: NULL pointer");
+    if (nomega < 1 || nroots < 1 || !(eta > 0) || !std::isfinite(eta))
+        return fail(nullptr, ADC_E_ARG, "adc_spectral_function: nomega, nroots >= 1, eta > 0");
+    return guarded(nullptr, [&]() {
+        adc::spectral_function((hipStream_t)stream, omega, nomega, energies, P, nroots, eta, A);
+        ADC_HIP(hipStreamSynchronize((hipStream_t)stream));
+        return ADC_OK;
+    });
+}
+
+int adc_propagator_diag(const double* omega, int nomega, const double* energies, const double* X,
+                        int nroots, int norb, double eta, double* G, void* stream) {
+    if (!omega || !energies || !X || !G)
+        return fail(nullptr, ADC_E_ARG, "adc_propagator_diag: NULL pointer");
+    if (nomega < 1 || nroots < 1 || norb < 1 || !(eta > 0) || !std::isfinite(eta))
+        return fail(nullptr, ADC_E_ARG, "adc_propagator_diag: sizes >= 1, eta > 0");
+    return guarded(nullptr, [&]() {
+        adc::propagator_diag((hipStream_t)stream, omega, nomega, energies, X, nroots, norb, eta, G);
+        ADC_HIP(hipStreamSynchronize((hipStream_t)stream));
         return ADC_OK;
     });
 }
@@ -636,6 +687,7 @@ void adc_destroy(adc_ctx* c) {
     for (hipEvent_t& e : c->E.tev)
         if (e) (void)hipEventDestroy(e);
     if (c->own_blas && c->E.blas) rocblas_destroy_handle(c->E.blas);
+    if (c->ttu_host) (void)hipHostFree(c->ttu_host);
     delete c;
 }
 

@@ -68,7 +68,16 @@ struct adc_ctx {
         // FP32 copies for the FP32-product level
         adc::DBuf<float> fttT1, fttT2, ftT1, ftD, foovvT, ftT;
         bool ready = false, ready_mixed = false, ready_f32 = false;
+        // the current call's path: 1 arranged operands resident, 2 built per
+        // call in blocks from t, (ov|ov) and (oo|vv) (option value 2, or the
+        // automatic choice when the resident ones do not fit)
+        int mode = 0;
+        bool ready_blocked = false;
     } eal;
+    // t~ + u~ parked in pinned host memory (the blocked EA path frees device
+    // memory for large systems); the spectroscopic amplitudes stream it back
+    double* ttu_host = nullptr;
+    bool big_mixed = false;   // FP32 copies of the O^2 V^2 operands made
     long long pp_slab_bytes = 16LL << 30;  // rebuilt four-index slab (particle-particle term)
     int pp_blocks = 0;                     // minimum number of a-blocks of that term (0: automatic)
     int pp_group = 0;                      // blocks per contraction product (0: automatic)
@@ -110,13 +119,29 @@ struct adc_ctx {
     double st_seconds = 0.0;
 
     std::string err;
+
+    // setup progress on stderr (adc_set_setup_option "verbose"): one line per
+    // phase and per block of the long loops, after synchronising the stream
+    int setup_verbose = 0;
+    std::chrono::steady_clock::time_point setup_t0;
+    void phase(const char* what, long long i = -1, long long n = -1) {
+        if (!setup_verbose) return;
+        (void)hipStreamSynchronize(E.stream);
+        const double s =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - setup_t0).count();
+        if (i >= 0)
+            fprintf(stderr, "adc_setup %8.1f s  %s %lld/%lld\n", s, what, i, n);
+        else
+            fprintf(stderr, "adc_setup %8.1f s  %s\n", s, what);
+    }
 };
 
 namespace adc {
 
 // setup.hip
 void setup_all(adc_ctx* c, const double* eps, const double* B);
-void build_mixed(adc_ctx* c);
+void build_mixed(adc_ctx* c, bool big = true);   // big: also the O^2 V^2 operands
+void ensure_tt(adc_ctx* c);                       // t~ resident again if it was released
 void setup_adc3(adc_ctx* c, const double* tt, const double* X1);
 
 // sigma.hip
@@ -137,11 +162,18 @@ void sigma_cost(const adc_ctx* c, int nvec, double* total, double* pp);
 // ea_layout.hip
 // level: 0 FP64, 1 BF16 products, 2 FP32 products
 bool ea_layout_use(adc_ctx* c, int level);      // arranged EA sigma path for this call?
+                                                // (sets eal.mode: 1 resident, 2 blocked)
 void ea_layout_build(adc_ctx* c, int level);    // make the arranged operands (once each)
 // P1[z][x][j][y] = Y[z][j][x][y], P2[z][x][j][y] = Y[z][j][y][x],
 // D = P2 - 2 P1, Pm = 2 P1 - P2 (storage TB), Dw = D (storage T); null outputs skipped
 template <typename T, typename TB>
 void ea_pairs(Engine& E, const T* Y, int nvec, int O, int V, TB* P1, TB* P2, TB* D, TB* Pm, T* Dw);
+
+// spectrum.hip
+void spectral_function(hipStream_t st, const double* w, int nw, const double* e, const double* P,
+                       int nr, double eta, double* A);
+void propagator_diag(hipStream_t st, const double* w, int nw, const double* e, const double* X,
+                     int nr, int norb, double eta, double* G);
 
 // spec.hip
 void spec_amplitudes(adc_ctx* c, const double* vecs, int nvec, double* Xout /*device [nvec][N]*/);
@@ -183,13 +215,16 @@ int solver_finish(Solver* s, double* energies, double* P, double* vecs, int* n_i
 
 // kernels shared by setup/sigma (elementwise.hip)
 void stage_block(Engine& E, const double* B, int Q, int N, int p0, int np, int q0, int nq,
-                 double* out);   // out[p][q][Q] = B[Q][p0+p][q0+q]
+                 double* out, int Qtot = 0, int Qoff = 0);
+// out[p][q][Qoff + Q] = B[Q][p0+p][q0+q] for the Q slices of B (rows of out hold Qtot)
 void divide_denom2(Engine& E, double* t, const double* eo, const double* ev, int O, int V,
                    double scale);  // t[i][j][a][b] *= scale / (e_i + e_j - e_a - e_b)
 void divide_denom1(Engine& E, double* s, const double* eo, const double* ev, int O, int V,
                    double scale);  // s[i][a] *= scale / (e_i - e_a)
 void mul_denom2(Engine& E, const double* t, double* out, const double* eo, const double* ev, int O,
-                int V);            // out = (e_a + e_b - e_i - e_j) t
+                int V, int i0 = 0, int ni = -1);
+// out = (e_a + e_b - e_i - e_j) t on rows i0 .. i0+ni-1 (ni < 0: to the end); t, out
+// point at row i0
 void mul_denom1(Engine& E, const double* s, double* out, const double* eo, const double* ev, int O,
                 int V);            // out = (e_a - e_i) s
 template <typename TI, typename TO>

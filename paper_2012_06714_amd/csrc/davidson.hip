@@ -303,6 +303,17 @@ struct Solver {
         block = std::max(block, nroots);
         block = (int)std::min<long long>(block, dim);
         max_space = c->max_space > 0 ? c->max_space : 8 * block;
+        if (c->max_space <= 0) {
+            // default bound: V and W within a quarter of the free device memory
+            // (large systems), but room for three blocks of vectors
+            size_t fr = 0, tot = 0;
+            if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+                const long long fit = (long long)(fr / 4 / (2 * sizeof(double) * (size_t)dim));
+                max_space = (int)std::max<long long>(3LL * block, std::min<long long>(max_space, fit));
+            } else {
+                (void)hipGetLastError();
+            }
+        }
         max_space = std::max(max_space, 2 * block);
         max_space = (int)std::min<long long>(max_space, dim);
         tol_e = c->tol_e;

@@ -120,18 +120,29 @@ static size_t layout_bytes(const adc_ctx* c, int level) {
 }
 
 bool ea_layout_use(adc_ctx* c, int level) {
+    c->eal.mode = 0;
     if (c->kind != ADC_EA || c->ea_layout == 0) return false;
-    if (c->order == 2 || c->ea_layout == 1) return true;
+    if (c->order == 2 || c->ea_layout == 1 || c->ea_layout == 2) {
+        c->eal.mode = c->order == 2 ? 1 : c->ea_layout;
+        return true;
+    }
+    c->eal.mode = 1;
     if (c->eal.ready && (level == 0 || (level == 1 && c->eal.ready_mixed) ||
                          (level == 2 && c->eal.ready_f32)))
         return true;
-    // automatic: the operands still to be made must fit in half the free memory
+    if (c->eal.ready_blocked) {   // once blocked, stay blocked (t~ may be released)
+        c->eal.mode = 2;
+        return true;
+    }
+    // automatic: the operands still to be made must fit in half the free memory,
+    // else their blocks are made per call
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
         (void)hipGetLastError();
-        return false;
+        fr = 0;
     }
-    return layout_bytes(c, level) <= fr / 2;
+    if (layout_bytes(c, level) > fr / 2) c->eal.mode = 2;
+    return true;
 }
 
 void ea_layout_build(adc_ctx* c, int level) {
@@ -146,7 +157,36 @@ void ea_layout_build(adc_ctx* c, int level) {
         c->Bvo.alloc(O * V * Q, &c->arena);
         permute<double>(E, 1.0, "kaQ", c->Bov.p, 0.0, "akQ", c->Bvo.p);
     }
-    if (!L.ready) {
+    if (L.mode == 2 && !L.ready && !L.ready_blocked) {
+        // blocked path: only the small operands stay resident; t~ and t~ + u~
+        // (read per call through t, and once per solve) leave the device
+        L.G.alloc(O * O * O * V, &c->arena);
+        permute<double>(E, -2.0, "jlka", c->ooov.p, 0.0, "ajkl", L.G.p);
+        permute<double>(E, 1.0, "jkla", c->ooov.p, 1.0, "ajkl", L.G.p);
+        ensure_tt(c);
+        L.H.alloc(O * V * Q, &c->arena);
+        ctr_sliced<double>(E, 1.0, "ikbd", c->tt.p, "kdQ", c->Bov.p, 0.0, "ibQ", L.H.p);
+        L.BH.alloc(O * V * Q, &c->arena);
+        ADC_HIP(hipMemcpyAsync(L.BH.p, c->Bov.p, O * V * Q * sizeof(double),
+                               hipMemcpyDeviceToDevice, E.stream));
+        axpy<double>(E, 1.0, L.H.p, L.BH.p, O * V * Q);
+        ADC_HIP(hipStreamSynchronize(E.stream));
+        c->tt.release();
+        // only the sliced contraction's own slots: this runs inside a sigma
+        // call whose input and result slots are already in use
+        for (int slot : {60, 61, 62}) E.scratch.erase(slot);
+        if (c->ttu.p && !c->ttu_host) {
+            void* h = nullptr;
+            ADC_HIP(hipHostMalloc(&h, c->ttu.bytes(), hipHostMallocDefault));
+            c->ttu_host = static_cast<double*>(h);
+            ADC_HIP(hipMemcpyAsync(h, c->ttu.p, c->ttu.bytes(), hipMemcpyDeviceToHost, E.stream));
+            ADC_HIP(hipStreamSynchronize(E.stream));
+            c->ttu.release();
+        }
+        L.ready_blocked = true;
+    }
+    if (L.mode == 1 && !L.ready) {
+        ensure_tt(c);
         L.ttT1.alloc(big, &c->arena);
         permute<double>(E, 1.0, "jkcd", c->tt.p, 0.0, "kdjc", L.ttT1.p);
         L.ttT2.alloc(big, &c->arena);
@@ -179,7 +219,7 @@ void ea_layout_build(adc_ctx* c, int level) {
         if (!L.fH.p) to_f32(c, L.H, L.fH);
         if (!L.fBH.p) to_f32(c, L.BH, L.fBH);
     }
-    if (level == 2 && !L.ready_f32) {
+    if (L.mode == 1 && level == 2 && !L.ready_f32) {
         to_f32(c, L.ttT1, L.fttT1);
         to_f32(c, L.ttT2, L.fttT2);
         to_f32(c, L.tT1, L.ftT1);
@@ -188,7 +228,7 @@ void ea_layout_build(adc_ctx* c, int level) {
         to_f32(c, L.tT, L.ftT);
         L.ready_f32 = true;
     }
-    if (level == 1) {
+    if (L.mode == 1 && level == 1) {
         if (!L.ready_mixed) {
             to_bf16(c, L.ttT1, L.httT1);
             to_bf16(c, L.ttT2, L.httT2);

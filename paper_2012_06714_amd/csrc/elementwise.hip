@@ -14,8 +14,9 @@ static unsigned nblk(long long n, int bs) {
 // ---------------------------------------------------------------------------
 // out[p][q][Q] = B[Q][p0+p][q0+q]   (transpose through a 32x33 LDS tile)
 // ---------------------------------------------------------------------------
+// B holds Q slices (Q <= Qtot); out[r][Qoff + q] with row length Qtot
 __global__ void k_stage(const double* __restrict__ B, double* __restrict__ out, int Q, int N, int p0,
-                        int np, int q0, int nq) {
+                        int np, int q0, int nq, int Qtot, int Qoff) {
     __shared__ double tile[32][33];
     const long long R = (long long)np * nq;
     const long long r0 = (long long)blockIdx.x * 32;
@@ -35,32 +36,37 @@ __global__ void k_stage(const double* __restrict__ B, double* __restrict__ out, 
     for (int k = ty; k < 32; k += 8) {
         long long r = r0 + k;
         int q = Q0 + tx;
-        if (r < R && q < Q) out[r * Q + q] = tile[tx][k];
+        if (r < R && q < Q) out[r * Qtot + Qoff + q] = tile[tx][k];
     }
 }
 
 void stage_block(Engine& E, const double* B, int Q, int N, int p0, int np, int q0, int nq,
-                 double* out) {
+                 double* out, int Qtot, int Qoff) {
+    if (Qtot <= 0) Qtot = Q;
     long long R = (long long)np * nq;
+    ADC_REQUIRE((Q + 31) / 32 <= 65535, "stage_block: too many auxiliary functions per call");
     dim3 grid(nblk(R, 32), (Q + 31) / 32);
-    hipLaunchKernelGGL(k_stage, grid, dim3(32, 8), 0, E.stream, B, out, Q, N, p0, np, q0, nq);
+    hipLaunchKernelGGL(k_stage, grid, dim3(32, 8), 0, E.stream, B, out, Q, N, p0, np, q0, nq, Qtot,
+                       Qoff);
     ADC_HIP(hipGetLastError());
 }
 
 // ---------------------------------------------------------------------------
 // denominators
 // ---------------------------------------------------------------------------
+// rows i0 .. i0 + ni - 1 of an [i][j][a][b] tensor (t and src point at row i0)
 __global__ void k_denom2(double* t, const double* __restrict__ eo, const double* __restrict__ ev,
-                         int O, int V, double scale, int mode, const double* __restrict__ src) {
+                         int O, int V, double scale, int mode, const double* __restrict__ src,
+                         int i0, int ni) {
     extern __shared__ double sev[];
     for (int a = threadIdx.x; a < V; a += blockDim.x) sev[a] = ev[a];
     __syncthreads();
     const long long VV = (long long)V * V;
-    const long long total = (long long)O * O * VV;
+    const long long total = (long long)ni * O * VV;
     for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < total;
          x += (long long)gridDim.x * blockDim.x) {
         long long ij = x / VV, ab = x - ij * VV;
-        int i = (int)(ij / O), j = (int)(ij - (long long)i * O);
+        int i = i0 + (int)(ij / O), j = (int)(ij - (ij / O) * O);
         int a = (int)(ab / V), b = (int)(ab - (long long)a * V);
         double d = eo[i] + eo[j] - sev[a] - sev[b];
         if (mode == 0)
@@ -74,15 +80,17 @@ void divide_denom2(Engine& E, double* t, const double* eo, const double* ev, int
                    double scale) {
     long long total = (long long)O * O * V * V;
     hipLaunchKernelGGL(k_denom2, dim3(nblk(total, 256)), dim3(256), V * sizeof(double), E.stream, t,
-                       eo, ev, O, V, scale, 0, (const double*)nullptr);
+                       eo, ev, O, V, scale, 0, (const double*)nullptr, 0, O);
     ADC_HIP(hipGetLastError());
 }
 
 void mul_denom2(Engine& E, const double* t, double* out, const double* eo, const double* ev, int O,
-                int V) {
-    long long total = (long long)O * O * V * V;
+                int V, int i0, int ni) {
+    if (ni < 0) ni = O - i0;
+    long long total = (long long)ni * O * V * V;
+    if (total == 0) return;
     hipLaunchKernelGGL(k_denom2, dim3(nblk(total, 256)), dim3(256), V * sizeof(double), E.stream,
-                       out, eo, ev, O, V, 1.0, 1, t);
+                       out, eo, ev, O, V, 1.0, 1, t, i0, ni);
     ADC_HIP(hipGetLastError());
 }
 

@@ -28,18 +28,31 @@ static void narrow(adc_ctx* c, const DBuf<double>& src, DBuf<TO>& dst) {
     ADC_HIP(hipGetLastError());
 }
 
-void build_mixed(adc_ctx* c) {
+// t~ = 2 t_ij^ab - t_ij^ba made again from t (the blocked EA path releases it)
+void ensure_tt(adc_ctx* c) {
+    if (c->tt.p || c->order != 3) return;
+    const size_t n = (size_t)c->O * c->O * c->V * c->V;
+    c->tt.alloc(n, &c->arena);
+    permute<double>(c->E, -1.0, "ijab", c->t.p, 0.0, "ijba", c->tt.p);
+    axpy<double>(c->E, 2.0, c->t.p, c->tt.p, n);
+}
+
+void build_mixed(adc_ctx* c, bool big) {
+    if (big && !c->big_mixed && c->order == 3) {
+        ensure_tt(c);
+        narrow(c, c->ovov, c->fovov);
+        narrow(c, c->oovv, c->foovv);
+        narrow(c, c->t, c->ft);
+        narrow(c, c->tt, c->ftt);
+        c->big_mixed = true;
+    }
     if (c->mixed_ready) return;
     narrow(c, c->Boo, c->fBoo);
     narrow(c, c->Bov, c->fBov);
     narrow(c, c->Bvo, c->fBvo);
     narrow(c, c->M11, c->fM11);
     if (c->order == 3) {
-        narrow(c, c->ovov, c->fovov);
-        narrow(c, c->oovv, c->foovv);
         narrow(c, c->ooov, c->fooov);
-        narrow(c, c->t, c->ft);
-        narrow(c, c->tt, c->ftt);
         narrow(c, c->gam, c->fgam);
         if (c->kind == ADC_EA) {
             narrow(c, c->Bvv, c->hBvv);

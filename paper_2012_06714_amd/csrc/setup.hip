@@ -22,6 +22,15 @@ namespace adc {
 
 namespace {
 
+bool is_device_pointer(const void* p) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice;
+}
+
 struct Tmp {
     DBuf<double> b;
     double* operator()(adc_ctx* c, size_t n) {
@@ -47,14 +56,16 @@ void setup_all(adc_ctx* c, const double* eps, const double* B) {
     E.ext.V = V;
     E.ext.Q = Q;
 
+    // eps and B may be device or host memory (copies of either kind go through
+    // hipMemcpyDefault); host B is staged in blocks of auxiliary functions
     c->eo.alloc(O, &c->arena);
     c->ev.alloc(V, &c->arena);
-    ADC_HIP(hipMemcpyAsync(c->eo.p, eps, O * sizeof(double), hipMemcpyDeviceToDevice, E.stream));
-    ADC_HIP(hipMemcpyAsync(c->ev.p, eps + O, V * sizeof(double), hipMemcpyDeviceToDevice, E.stream));
+    ADC_HIP(hipMemcpyAsync(c->eo.p, eps, O * sizeof(double), hipMemcpyDefault, E.stream));
+    ADC_HIP(hipMemcpyAsync(c->ev.p, eps + O, V * sizeof(double), hipMemcpyDefault, E.stream));
     {
         // energy scale of the learned preconditioner's features: max |eps|
         std::vector<double> h(N);
-        ADC_HIP(hipMemcpyAsync(h.data(), eps, N * sizeof(double), hipMemcpyDeviceToHost, E.stream));
+        ADC_HIP(hipMemcpyAsync(h.data(), eps, N * sizeof(double), hipMemcpyDefault, E.stream));
         ADC_HIP(hipStreamSynchronize(E.stream));
         double s = 0.0;
         for (double v : h) s = std::max(s, std::fabs(v));
@@ -65,11 +76,29 @@ void setup_all(adc_ctx* c, const double* eps, const double* B) {
     c->Boo.alloc(OO * Q, &c->arena);
     c->Bov.alloc(OV * Q, &c->arena);
     c->Bvv.alloc(VV * Q, &c->arena);
-    stage_block(E, B, Q, N, 0, O, 0, O, c->Boo.p);
-    stage_block(E, B, Q, N, 0, O, O, V, c->Bov.p);
-    stage_block(E, B, Q, N, O, V, O, V, c->Bvv.p);
+    if (is_device_pointer(B)) {
+        stage_block(E, B, Q, N, 0, O, 0, O, c->Boo.p);
+        stage_block(E, B, Q, N, 0, O, O, V, c->Bov.p);
+        stage_block(E, B, Q, N, O, V, O, V, c->Bvv.p);
+    } else {
+        // blocks of auxiliary functions through a device buffer of <= 1 GiB
+        const long long NN = (long long)N * N;
+        const int nq = (int)std::max<long long>(1, std::min<long long>(Q, (1LL << 27) / NN));
+        DBuf<double> buf;
+        buf.alloc((size_t)(nq * NN), &c->arena);
+        for (int q0 = 0; q0 < Q; q0 += nq) {
+            const int n = std::min(nq, Q - q0);
+            ADC_HIP(hipMemcpyAsync(buf.p, B + (size_t)q0 * NN, (size_t)n * NN * sizeof(double),
+                                   hipMemcpyDefault, E.stream));
+            stage_block(E, buf.p, n, N, 0, O, 0, O, c->Boo.p, Q, q0);
+            stage_block(E, buf.p, n, N, 0, O, O, V, c->Bov.p, Q, q0);
+            stage_block(E, buf.p, n, N, O, V, O, V, c->Bvv.p, Q, q0);
+            ADC_HIP(hipStreamSynchronize(E.stream));   // the buffer is refilled next
+        }
+    }
     c->rho.alloc(0, &c->arena);
 
+    c->phase("DF factors staged");
     // integral blocks
     c->ovov.alloc(OV * OV, &c->arena);
     ctr<double>(E, 1.0, "iaQ", c->Bov.p, "jbQ", c->Bov.p, 0.0, "iajb", c->ovov.p);
@@ -81,10 +110,12 @@ void setup_all(adc_ctx* c, const double* eps, const double* B) {
     permute<double>(E, 1.0, "iajb", c->ovov.p, 0.0, "ijab", c->t.p);
     divide_denom2(E, c->t.p, c->eo.p, c->ev.p, O, V, 1.0);
 
-    Tmp ttb;
-    double* tt = ttb(c, OO * VV);
+    // t~ stays resident (the sigma contractions read it)
+    c->tt.alloc(OO * VV, &c->arena);
+    double* tt = c->tt.p;
     tilde(c, c->t.p, tt);
 
+    c->phase("first-order doubles");
     // second-order singles: R_ia = -2 t_kl^ca (li|kc) + t_kl^ca (lc|ki) + t~_ik^cd (kd|ac),
     // s = -R / (e_a - e_i)
     c->s.alloc(OV, &c->arena);
@@ -92,9 +123,9 @@ void setup_all(adc_ctx* c, const double* eps, const double* B) {
     double* X = xb(c, OV * Q);   // X1[i][c][Q] = t~_ik^cd B^Q_kd (reused at third order)
     {
         double* R = c->s.p;
-        ctr<double>(E, -2.0, "klca", c->t.p, "likc", c->ooov.p, 0.0, "ia", R);
-        ctr<double>(E, 1.0, "klca", c->t.p, "kilc", c->ooov.p, 1.0, "ia", R);
-        ctr<double>(E, 1.0, "ikcd", tt, "kdQ", c->Bov.p, 0.0, "icQ", X);
+        ctr_sliced<double>(E, -2.0, "klca", c->t.p, "likc", c->ooov.p, 0.0, "ia", R);
+        ctr_sliced<double>(E, 1.0, "klca", c->t.p, "kilc", c->ooov.p, 1.0, "ia", R);
+        ctr_sliced<double>(E, 1.0, "ikcd", tt, "kdQ", c->Bov.p, 0.0, "icQ", X);
         ctr<double>(E, 1.0, "icQ", X, "acQ", c->Bvv.p, 1.0, "ia", R);
         divide_denom1(E, R, c->eo.p, c->ev.p, O, V, 1.0);
     }
@@ -108,13 +139,13 @@ void setup_all(adc_ctx* c, const double* eps, const double* B) {
         double* tau = tb(c, (size_t)n1 * n1);
         if (ea) {
             // tau_ab = t_jk^ca [2 (jc|kb) - (jb|kc)]
-            ctr<double>(E, 2.0, "jkca", c->t.p, "jckb", c->ovov.p, 0.0, "ab", tau);
-            ctr<double>(E, -1.0, "jkca", c->t.p, "jbkc", c->ovov.p, 1.0, "ab", tau);
+            ctr_sliced<double>(E, 2.0, "jkca", c->t.p, "jckb", c->ovov.p, 0.0, "ab", tau);
+            ctr_sliced<double>(E, -1.0, "jkca", c->t.p, "jbkc", c->ovov.p, 1.0, "ab", tau);
             symmetrize_m11(E, c->M11.p, tau, c->ev.p, V, 1.0);
         } else {
             // kappa_ij = t_ik^bc [2 (jb|kc) - (jc|kb)]
-            ctr<double>(E, 2.0, "ikbc", c->t.p, "jbkc", c->ovov.p, 0.0, "ij", tau);
-            ctr<double>(E, -1.0, "ikbc", c->t.p, "jckb", c->ovov.p, 1.0, "ij", tau);
+            ctr_sliced<double>(E, 2.0, "ikbc", c->t.p, "jbkc", c->ovov.p, 0.0, "ij", tau);
+            ctr_sliced<double>(E, -1.0, "ikbc", c->t.p, "jckb", c->ovov.p, 1.0, "ij", tau);
             symmetrize_m11(E, c->M11.p, tau, c->eo.p, O, -1.0);
         }
     }
@@ -123,21 +154,23 @@ void setup_all(adc_ctx* c, const double* eps, const double* B) {
     c->rho.alloc((size_t)n1 * n1, &c->arena);
     if (ea) {
         // rho_ce = -1/2 t_kl^de t~_lk^cd
-        ctr<double>(E, -1.0, "klde", c->t.p, "lkcd", c->t.p, 0.0, "ce", c->rho.p);
-        ctr<double>(E, 0.5, "klde", c->t.p, "lkdc", c->t.p, 1.0, "ce", c->rho.p);
+        ctr_sliced<double>(E, -1.0, "klde", c->t.p, "lkcd", c->t.p, 0.0, "ce", c->rho.p);
+        ctr_sliced<double>(E, 0.5, "klde", c->t.p, "lkdc", c->t.p, 1.0, "ce", c->rho.p);
     } else {
         // rho_jm = -1/2 t_jk^bc t~_km^cb
-        ctr<double>(E, -1.0, "jkbc", c->t.p, "kmcb", c->t.p, 0.0, "jm", c->rho.p);
-        ctr<double>(E, 0.5, "jkbc", c->t.p, "kmbc", c->t.p, 1.0, "jm", c->rho.p);
+        ctr_sliced<double>(E, -1.0, "jkbc", c->t.p, "kmcb", c->t.p, 0.0, "jm", c->rho.p);
+        ctr_sliced<double>(E, 0.5, "jkbc", c->t.p, "kmbc", c->t.p, 1.0, "jm", c->rho.p);
     }
 
+    c->phase("second-order singles, 1p-1p / 1h-1h block and rho");
     if (c->order == 3) setup_adc3(c, tt, X);
+    else c->tt.release();   // ADC(2) sigma does not read t~
 
-    // IP sigma reads B^Q_ai with the virtual index leading
+    // IP sigma reads B^Q_ai with the virtual index leading, and never the vv block
     if (!ea) {
         c->Bvo.alloc(OV * Q, &c->arena);
         permute<double>(E, 1.0, "iaQ", c->Bov.p, 0.0, "aiQ", c->Bvo.p);
-        if (c->order == 2) c->Bvv.release();   // IP-ADC(2) never reads the vv block
+        c->Bvv.release();
     }
 
     // ADC(2) needs the (ov|ov) and (oo|ov) blocks only for the amplitudes and
@@ -158,6 +191,7 @@ void setup_all(adc_ctx* c, const double* eps, const double* B) {
         diag22_adc2(E, c->diag.p, n1, V, O, c->ev.p, c->eo.p, 1.0, -1.0);
     ADC_HIP(hipStreamSynchronize(E.stream));
     E.scratch.clear();
+    c->phase("diagonal: setup done");
 }
 
 }  // namespace adc

@@ -8,6 +8,7 @@
 #include "context.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 
 namespace adc {
@@ -183,18 +184,19 @@ static void sigma_adc3_ip_terms(adc_ctx* c, const Views<T>& v, const T* Y1, cons
 
 
 template <typename T>
-static Views<T> views(adc_ctx* c);
+static Views<T> views(adc_ctx* c, bool big = true);
 
 template <>
-Views<double> views<double>(adc_ctx* c) {
+Views<double> views<double>(adc_ctx* c, bool big) {
+    if (big) ensure_tt(c);
     return Views<double>{c->Boo.p,  c->Bov.p,  c->Bvo.p,  c->Bvv.p, c->M11.p,
                          c->ovov.p, c->oovv.p, c->ooov.p, c->oooo.p, c->t.p,
                          c->tt.p,   c->gam.p,  c->Om.p,   c->Pi.p};
 }
 
 template <>
-Views<float> views<float>(adc_ctx* c) {
-    build_mixed(c);
+Views<float> views<float>(adc_ctx* c, bool big) {
+    build_mixed(c, big);
     return Views<float>{c->fBoo.p,  c->fBov.p,  c->fBvo.p,  c->fBvv.p, c->fM11.p,
                         c->fovov.p, c->foovv.p, c->fooov.p, c->foooo.p, c->ft.p,
                         c->ftt.p,   c->fgam.p,  c->fOm.p,   c->fPi.p};
@@ -247,7 +249,95 @@ static GemmOut omap(long long rsplit, long long rs1, long long rs2, long long cs
     return o;
 }
 
-enum ArrSlot { A_P1 = 40, A_P2, A_PM = 43, A_DW, A_W, A_X1, A_F2, A_W2, A_X, A_RP = 51, A_WK };
+enum ArrSlot { A_P1 = 40, A_P2, A_PM = 43, A_DW, A_W, A_X1, A_F2, A_W2, A_X, A_RP = 51, A_WK,
+               A_SLICE = 70 };
+
+// ---------------------------------------------------------------------------
+// blocked products: arranged operands built per call, one block at a time
+// ---------------------------------------------------------------------------
+// out[x][y][z][w] (x < n) = al src[(x0+x) s0 + y s1 + z s2 + w s3]
+//                         + be src[(x0+x) r0 + y r1 + z r2 + w r3]
+// (the block of an operand rearranged from a resident FP64 tensor, rounded to
+// the product's storage type: BF16 through FP32, as the resident copies are)
+struct ArrSpec {
+    const double* src;
+    long long e1, e2, e3;
+    long long s[4], r[4];
+    double al, be;
+};
+
+template <typename TB>
+__device__ __forceinline__ TB narrow_to(double v) {
+    if constexpr (sizeof(TB) == 2)
+        return (TB)(float)v;
+    else
+        return (TB)v;
+}
+
+template <typename TB>
+__global__ void k_arrange(ArrSpec a, long long x0, long long total, TB* __restrict__ out) {
+    for (long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x; o < total;
+         o += (long long)gridDim.x * blockDim.x) {
+        long long q = o;
+        const long long w = q % a.e3;
+        q /= a.e3;
+        const long long z = q % a.e2;
+        q /= a.e2;
+        const long long y = q % a.e1;
+        const long long x = q / a.e1 + x0;
+        double v = a.al * a.src[x * a.s[0] + y * a.s[1] + z * a.s[2] + w * a.s[3]];
+        if (a.be != 0.0) v += a.be * a.src[x * a.r[0] + y * a.r[1] + z * a.r[2] + w * a.r[3]];
+        out[o] = narrow_to<TB>(v);
+    }
+}
+
+static ArrSpec arr(const double* src, long long e1, long long e2, long long e3,
+                   std::array<long long, 4> s, double al = 1.0,
+                   std::array<long long, 4> r = {0, 0, 0, 0}, double be = 0.0) {
+    ArrSpec a;
+    a.src = src;
+    a.e1 = e1;
+    a.e2 = e2;
+    a.e3 = e3;
+    for (int k = 0; k < 4; ++k) {
+        a.s[k] = s[k];
+        a.r[k] = r[k];
+    }
+    a.al = al;
+    a.be = be;
+    return a;
+}
+
+// One NT product whose operand A (arranged_a) or B is the arranged tensor of
+// `nlead` leading indices, each of e1 rows of K = e2 e3 elements; run in
+// blocks of leading indices, each block of the result stored at C + x0 c_off
+// through the same output map.
+template <typename TB, typename TO>
+static void blocked_nt(adc_ctx* c, bool arranged_a, long long M_or_N, const ArrSpec& a,
+                       long long nlead, double alpha, const TB* other, long long ld_other,
+                       double beta, TO* C, GemmOut map, long long c_off) {
+    Engine& E = c->E;
+    const long long rows = a.e1, K = a.e2 * a.e3;
+    const long long per = rows * K * (long long)sizeof(TB);
+    const long long nb =
+        std::max<long long>(1, std::min<long long>(nlead, E.slice_budget * 8 / per));
+    TB* sl = (TB*)E.scratch.get(A_SLICE, (size_t)(nb * rows * K) * sizeof(TB));
+    for (long long x0 = 0; x0 < nlead; x0 += nb) {
+        const long long n = std::min(nb, nlead - x0);
+        const long long total = n * rows * K;
+        long long g = (total + 255) / 256;
+        g = std::max<long long>(1, std::min<long long>(g, 1LL << 20));
+        hipLaunchKernelGGL(k_arrange<TB>, dim3((unsigned)g), dim3(256), 0, E.stream, a, x0, total,
+                           sl);
+        ADC_HIP(hipGetLastError());
+        if (arranged_a)
+            gemm_map<TB, TO>(E, false, true, n * rows, M_or_N, K, alpha, sl, K, other, ld_other,
+                             beta, C + x0 * c_off, map);
+        else
+            gemm_map<TB, TO>(E, false, true, M_or_N, n * rows, K, alpha, other, ld_other, sl, K,
+                             beta, C + x0 * c_off, map);
+    }
+}
 
 // EA sigma (ADC(2) terms and, for ADC(3), the second-order coupling and the
 // first-order 2p1h-2p1h terms; the particle-particle term is applied
@@ -266,7 +356,8 @@ template <typename T, typename TB>
 static void sigma_ea_arranged(adc_ctx* c, const T* Y1, const T* Y2, T* S1, T* S2, int nvec) {
     Engine& E = c->E;
     ea_layout_build(c, level_of<T, TB>());
-    const Views<T> v = views<T>(c);
+    const bool blocked = c->eal.mode == 2;
+    const Views<T> v = views<T>(c, !blocked);
     const long long Z = nvec, O = c->O, V = c->V, Q = c->Q;
     const long long OV = O * V, VV = V * V, OVV = O * VV;
     const size_t n4 = (size_t)(Z * OVV);
@@ -298,20 +389,42 @@ static void sigma_ea_arranged(adc_ctx* c, const T* Y1, const T* Y2, T* S1, T* S2
     if (o3) {
         const EaOps<T, TB> a = ea_ops(c, (T*)nullptr, (TB*)nullptr);
         BW = a.BH;
+        // the arranged operands of the blocked path, from the resident FP64 t,
+        // (ov|ov) and (oo|vv) (strides of t[j][k][c][d] = t_jk^cd: O V^2, V^2, V, 1)
+        const double *t = c->t.p, *ovv = c->ovov.p, *oov = c->oovv.p;
+        const long long s0 = OVV, s1 = VV;
+        // t~_jk^cd as [k][d][j][c] and t~_jk^dc as [k][d][j][c]
+        const ArrSpec tt1 = arr(t, V, O, V, {s1, 1, s0, V}, 2.0, {s1, V, s0, 1}, -1.0);
+        const ArrSpec tt2 = arr(t, V, O, V, {s1, V, s0, 1}, 2.0, {s1, 1, s0, V}, -1.0);
+        const ArrSpec t1 = arr(t, V, O, V, {s1, 1, s0, V});          // t_jk^cd [k][d][j][c]
+        const ArrSpec tD = arr(t, V, O, V, {s0, 1, s1, V});          // t_ik^da [i][a][k][d]
+        const ArrSpec oT = arr(oov, V, O, V, {s1, V, s0, 1});        // (ji|bc) [i][b][j][c]
+        const ArrSpec tTa = arr(t, V, O, O, {V, 1, s0, s1});         // t_kl^ab [a][b][k][l]
+        const ArrSpec ovI = arr(ovv, V, O, V, {s0, O * V, V, 1});    // (ov|ov) as it is
+        const ArrSpec tI = arr(t, O, V, V, {s0, s1, V, 1});          // t as it is
         // sigma_a += sum_jb (Y_baj - 2 Y_abj) Gamma_jb
         gemm_map<T, T>(E, false, true, Z * V, 1, OV, 1.0, Dw, OV, v.gam, OV, 1.0, S1,
                        GemmOut::rowmajor(1));
         // sigma_a -= sum_jkl Y_bcj t_kl^bc [2 (jl|ka) - (jk|la)]
         T* X1 = slot<T>(E, A_X1, (size_t)(Z * O * O * O));
-        gemm_map<T, T>(E, false, true, Z * O, O * O, VV, 1.0, Y2, VV, v.t, VV, 0.0, X1,
-                       GemmOut::rowmajor(O * O));
+        if (!blocked || sizeof(T) == 8)
+            gemm_map<T, T>(E, false, true, Z * O, O * O, VV, 1.0, Y2, VV,
+                           blocked ? (const T*)c->t.p : v.t, VV, 0.0, X1, GemmOut::rowmajor(O * O));
+        else
+            blocked_nt<T, T>(c, false, Z * O, tI, O, 1.0, Y2, VV, 0.0, X1,
+                             GemmOut::rowmajor(O * O), O);
         gemm_map<T, T>(E, false, true, Z, V, O * O * O, 1.0, X1, O * O * O, a.G, O * O * O, 1.0,
                        S1, GemmOut::rowmajor(V));
         // F2 = A~ + C~ as F2[z][k][b][d], then sigma_a += sum_kQ (sum_bd F2 (bd|Q)) (ka|Q)
         T* F2 = slot<T>(E, A_F2, n4);
         const GemmOut f2map = omap(V, OVV, V, V, VV, 1);
-        gemm_map<TB, T>(E, false, true, Z * V, OV, OV, 1.0, P1, OV, a.ttT1, OV, 0.0, F2, f2map);
-        gemm_map<TB, T>(E, false, true, Z * V, OV, OV, 1.0, P2, OV, a.ttT2, OV, 1.0, F2, f2map);
+        if (blocked) {
+            blocked_nt<TB, T>(c, false, Z * V, tt1, O, 1.0, P1, OV, 0.0, F2, f2map, VV);
+            blocked_nt<TB, T>(c, false, Z * V, tt2, O, 1.0, P2, OV, 1.0, F2, f2map, VV);
+        } else {
+            gemm_map<TB, T>(E, false, true, Z * V, OV, OV, 1.0, P1, OV, a.ttT1, OV, 0.0, F2, f2map);
+            gemm_map<TB, T>(E, false, true, Z * V, OV, OV, 1.0, P2, OV, a.ttT2, OV, 1.0, F2, f2map);
+        }
         T* W2 = slot<T>(E, A_W2, (size_t)(Z * O * Q));
         gemm_map<T, T>(E, false, false, Z * O, Q, VV, 1.0, F2, VV, v.Bvv, Q, 0.0, W2,
                        GemmOut::rowmajor(Q));
@@ -323,8 +436,12 @@ static void sigma_ea_arranged(adc_ctx* c, const T* Y1, const T* Y2, T* S1, T* S2
         TB* X = slot<TB>(E, A_X, (size_t)(Z * O * O * O));
         gemm_map<T, TB>(E, false, true, Z, O * O * O, V, 1.0, Y1, V, v.ooov, V, 0.0, X,
                         omap(0, 0, O * O * O, O * O, 1, O));
-        gemm_map<TB, T>(E, false, true, Z * O, VV, O * O, -1.0, X, O * O, a.tT, O * O, 1.0, S2,
-                        GemmOut::rowmajor(VV));
+        if (blocked)
+            blocked_nt<TB, T>(c, false, Z * O, tTa, V, -1.0, X, O * O, 1.0, S2,
+                              GemmOut::rowmajor(VV), V);
+        else
+            gemm_map<TB, T>(E, false, true, Z * O, VV, O * O, -1.0, X, O * O, a.tT, O * O, 1.0, S2,
+                            GemmOut::rowmajor(VV));
         // sigma_abi -= sum_kd [(ac|kd) Y_c] t~_ik^bd = sum_Q U[a][z][Q] H[i][b][Q]
         gemm_map<T, T>(E, false, true, V * Z, OV, Q, -1.0, U, Q, a.H, Q, 1.0, S2,
                        omap(Z, V, OVV, V, VV, 1));
@@ -334,12 +451,25 @@ static void sigma_ea_arranged(adc_ctx* c, const T* Y1, const T* Y2, T* S1, T* S2
         TB* Rp = slot<TB>(E, A_RP, n4);
         gemm_map<T, TB>(E, false, true, Z * O, VV, Q, 1.0, Wk, Q, v.Bvv, Q, 0.0, Rp,
                         omap(O, OVV, V, V, OV, 1));
-        gemm_map<TB, T>(E, false, true, Z * V, OV, OV, 1.0, Rp, OV, a.tT1, OV, 1.0, S2, S2_zaib);
-        gemm_map<TB, T>(E, false, true, OV, Z * V, OV, 1.0, a.tD, OV, Rp, OV, 1.0, S2, S2_iazb);
-        // first-order 2p1h-2p1h: (2 Y_acj - Y_caj)(jc|ib) - Y_acj (ji|bc) - Y_cbj (ji|ac)
-        gemm_map<TB, T>(E, false, true, Z * V, OV, OV, 1.0, Pm, OV, a.ovov, OV, 1.0, S2, S2_zaib);
-        gemm_map<TB, T>(E, false, true, Z * V, OV, OV, -1.0, P1, OV, a.oovvT, OV, 1.0, S2, S2_zaib);
-        gemm_map<TB, T>(E, false, true, OV, Z * V, OV, -1.0, a.oovvT, OV, P2, OV, 1.0, S2, S2_iazb);
+        if (blocked) {
+            blocked_nt<TB, T>(c, false, Z * V, t1, O, 1.0, Rp, OV, 1.0, S2, S2_zaib, VV);
+            blocked_nt<TB, T>(c, true, Z * V, tD, O, 1.0, Rp, OV, 1.0, S2, S2_iazb, VV);
+            // first-order 2p1h-2p1h: (2 Y_acj - Y_caj)(jc|ib) - Y_acj (ji|bc) - Y_cbj (ji|ac)
+            if (sizeof(TB) == 8)
+                gemm_map<TB, T>(E, false, true, Z * V, OV, OV, 1.0, Pm, OV, (const TB*)ovv, OV,
+                                1.0, S2, S2_zaib);
+            else
+                blocked_nt<TB, T>(c, false, Z * V, ovI, O, 1.0, Pm, OV, 1.0, S2, S2_zaib, VV);
+            blocked_nt<TB, T>(c, false, Z * V, oT, O, -1.0, P1, OV, 1.0, S2, S2_zaib, VV);
+            blocked_nt<TB, T>(c, true, Z * V, oT, O, -1.0, P2, OV, 1.0, S2, S2_iazb, VV);
+        } else {
+            gemm_map<TB, T>(E, false, true, Z * V, OV, OV, 1.0, Rp, OV, a.tT1, OV, 1.0, S2, S2_zaib);
+            gemm_map<TB, T>(E, false, true, OV, Z * V, OV, 1.0, a.tD, OV, Rp, OV, 1.0, S2, S2_iazb);
+            // first-order 2p1h-2p1h: (2 Y_acj - Y_caj)(jc|ib) - Y_acj (ji|bc) - Y_cbj (ji|ac)
+            gemm_map<TB, T>(E, false, true, Z * V, OV, OV, 1.0, Pm, OV, a.ovov, OV, 1.0, S2, S2_zaib);
+            gemm_map<TB, T>(E, false, true, Z * V, OV, OV, -1.0, P1, OV, a.oovvT, OV, 1.0, S2, S2_zaib);
+            gemm_map<TB, T>(E, false, true, OV, Z * V, OV, -1.0, a.oovvT, OV, P2, OV, 1.0, S2, S2_iazb);
+        }
     }
     // sigma_a += sum_cQ (ac|Q) W[z][c][Q],  W = sum_jb D[z][c][j][b] [(jb|Q) + H_jb^Q]
     // (ADC(2): no H)
@@ -358,7 +488,8 @@ void sigma_block(adc_ctx* c, const double* X, double* Yout, int nvec) {
     const int np = (int)c->n2p;
     const long long len2 = nx * np * np;
     const long long dim = c->dim;
-    Views<T> v = views<T>(c);
+    const bool arranged = ea_layout_use(c, level_of<T, TB>());
+    Views<T> v = views<T>(c, !(arranged && c->eal.mode == 2));
     // FP32 contractions multiply in BF16 on the matrix cores in the mixed mode
     struct Bf16Scope {
         Engine& e;
@@ -378,7 +509,7 @@ void sigma_block(adc_ctx* c, const double* X, double* Yout, int nvec) {
 
     const bool ea3 = c->order == 3 && c->kind == ADC_EA;
     const bool ip3 = c->order == 3 && c->kind == ADC_IP;
-    if (ea_layout_use(c, level_of<T, TB>())) {
+    if (arranged) {
         sigma_ea_arranged<T, TB>(c, Y1, Y2, S1, S2, nvec);
     } else {
         sigma_adc2_terms<T>(c, v, Y1, Y2, S1, S2, nvec);

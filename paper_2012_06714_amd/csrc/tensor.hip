@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
 
 namespace adc {
 
@@ -558,6 +559,189 @@ void convert_f2d(Engine& E, const float* in, double* out, size_t n, double beta)
     hipLaunchKernelGGL(k_f2d, dim3(grid_for(n)), dim3(256), 0, E.stream, in, out, n, beta);
     ADC_HIP(hipGetLastError());
 }
+
+// ---------------------------------------------------------------------------
+// contraction over sliced views, bounded temporaries
+// ---------------------------------------------------------------------------
+// out[sum_k idx_k ostr_k] = in[o] for the contiguous input (row-major over dim)
+template <typename T>
+__global__ void k_scatter(const T* __restrict__ in, T* __restrict__ out, PermArgs a,
+                          long long total) {
+    for (long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x; o < total;
+         o += (long long)gridDim.x * blockDim.x) {
+        long long r = o, off = 0;
+        for (int k = a.nd - 1; k >= 0; --k) {
+            long long q = r / a.dim[k];
+            off += (r - q * a.dim[k]) * a.istr[k];
+            r = q;
+        }
+        out[off] = in[o];
+    }
+}
+
+namespace {
+
+// An operand as seen by a sliced contraction: its letters, the tensor's full
+// row-major strides, the extent of each axis inside the slice, and the
+// element offset of the slice's first element.
+struct SView {
+    std::string s;
+    long long str[8], n[8];
+    long long off = 0;
+    long long size() const {
+        long long z = 1;
+        for (size_t k = 0; k < s.size(); ++k) z *= n[k];
+        return z;
+    }
+    bool contiguous() const {
+        long long st = 1;
+        for (int k = (int)s.size() - 1; k >= 0; --k) {
+            if (n[k] > 1 && str[k] != st) return false;
+            st *= n[k];
+        }
+        return true;
+    }
+};
+
+SView make_view(const Engine& E, const char* s, const std::vector<Slice>& sl) {
+    SView v;
+    v.s = s;
+    const int nd = (int)v.s.size();
+    ADC_REQUIRE(nd <= 8, "sliced contraction: rank > 8");
+    long long st = 1;
+    for (int k = nd - 1; k >= 0; --k) {
+        v.str[k] = st;
+        v.n[k] = E.ext.of(v.s[k]);
+        st *= v.n[k];
+    }
+    for (const Slice& x : sl)
+        for (int k = 0; k < nd; ++k)
+            if (v.s[k] == x.c) {
+                v.off += x.lo * v.str[k];
+                v.n[k] = x.n;
+            }
+    return v;
+}
+
+PermArgs view_args(const SView& v) {
+    PermArgs a;
+    a.nd = (int)v.s.size();
+    for (int k = 0; k < a.nd; ++k) {
+        a.dim[k] = v.n[k];
+        a.istr[k] = v.str[k];
+    }
+    return a;
+}
+
+}  // namespace
+
+template <typename T>
+static void ctr_leaf(Engine& E, T alpha, const SView& va, const T* A, const SView& vb, const T* B,
+                     T beta, const SView& vc, T* C) {
+    // letters whose slice is shorter than the tensor's extent get placeholder
+    // names with the slice's extent (the same letter is sliced alike everywhere)
+    std::map<char, char> ren;
+    std::map<char, long long> saved;
+    const char pool[] = "0123456789!#$%&*+-./:;<=>?";
+    int next = 0;
+    auto rename = [&](const SView& v) {
+        std::string out = v.s;
+        for (size_t k = 0; k < v.s.size(); ++k) {
+            const char c = v.s[k];
+            if (v.n[k] == E.ext.of(c) && !ren.count(c)) continue;
+            if (!ren.count(c)) {
+                ADC_REQUIRE(pool[next] != 0, "sliced contraction: too many sliced letters");
+                ren[c] = pool[next++];
+            }
+            out[k] = ren[c];
+        }
+        return out;
+    };
+    // first pass: decide renamings from every view, then build the strings
+    rename(va);
+    rename(vb);
+    rename(vc);
+    const std::string sa = rename(va), sb = rename(vb), sc = rename(vc);
+    for (auto& kv : ren) {
+        long long n = -1;
+        for (const SView* v : {&va, &vb, &vc})
+            for (size_t k = 0; k < v->s.size(); ++k)
+                if (v->s[k] == kv.first) n = v->n[k];
+        auto it = E.ext.extra.find(kv.second);
+        if (it != E.ext.extra.end()) saved[kv.second] = it->second;
+        E.ext.extra[kv.second] = n;
+    }
+    struct Restore {
+        Engine& e;
+        std::map<char, char>& r;
+        std::map<char, long long>& s;
+        ~Restore() {
+            for (auto& kv : r) e.ext.extra.erase(kv.second);
+            for (auto& kv : s) e.ext.extra[kv.first] = kv.second;
+        }
+    } restore{E, ren, saved};
+    auto gathered = [&](const SView& v, const T* p, int slot) -> const T* {
+        if (v.contiguous()) return p + v.off;
+        T* tmp = (T*)E.scratch.get(slot, sizeof(T) * v.size());
+        const long long total = v.size();
+        hipLaunchKernelGGL(k_permute<T>, dim3(grid_for(total)), dim3(256), 0, E.stream,
+                           p + v.off, tmp, view_args(v), total, T(1), T(0));
+        ADC_HIP(hipGetLastError());
+        return tmp;
+    };
+    const T* Ap = gathered(va, A, 60);
+    const T* Bp = gathered(vb, B, 61);
+    if (vc.contiguous()) {
+        ctr<T>(E, alpha, sa.c_str(), Ap, sb.c_str(), Bp, beta, sc.c_str(), C + vc.off);
+        return;
+    }
+    T* Ct = beta == T(0) ? (T*)E.scratch.get(62, sizeof(T) * vc.size())
+                         : const_cast<T*>(gathered(vc, C, 62));
+    ctr<T>(E, alpha, sa.c_str(), Ap, sb.c_str(), Bp, beta, sc.c_str(), Ct);
+    const long long total = vc.size();
+    hipLaunchKernelGGL(k_scatter<T>, dim3(grid_for(total)), dim3(256), 0, E.stream, Ct,
+                       C + vc.off, view_args(vc), total);
+    ADC_HIP(hipGetLastError());
+}
+
+template <typename T>
+void ctr_sliced(Engine& E, T alpha, const char* sa, const T* A, const char* sb, const T* B, T beta,
+                const char* sc, T* C, const std::vector<Slice>& sl, long long budget) {
+    if (budget <= 0) budget = E.slice_budget;
+    const SView va = make_view(E, sa, sl), vb = make_view(E, sb, sl), vc = make_view(E, sc, sl);
+    const SView* big = &va;
+    for (const SView* v : {&vb, &vc})
+        if (v->size() > big->size()) big = v;
+    if (big->size() <= budget || va.size() == 0 || vb.size() == 0 || vc.size() == 0) {
+        ctr_leaf<T>(E, alpha, va, A, vb, B, beta, vc, C);
+        return;
+    }
+    // split the largest view along its longest axis: a free letter gives
+    // disjoint output slices, a summed one partial sums added in block order
+    int kbest = -1;
+    for (size_t k = 0; k < big->s.size(); ++k)
+        if (big->n[k] > 1 && (kbest < 0 || big->n[k] > big->n[kbest])) kbest = (int)k;
+    ADC_REQUIRE(kbest >= 0, "sliced contraction: nothing to split");
+    const char c = big->s[kbest];
+    long long lo0 = 0;
+    for (const Slice& x : sl)
+        if (x.c == c) lo0 = x.lo;
+    const long long n = big->n[kbest];
+    const long long parts = std::min(n, (big->size() + budget - 1) / budget);
+    const long long nb = (n + parts - 1) / parts;
+    const bool summed = strchr(sc, c) == nullptr;
+    for (long long b = 0; b < n; b += nb) {
+        std::vector<Slice> s2;
+        for (const Slice& x : sl)
+            if (x.c != c) s2.push_back(x);
+        s2.push_back({c, lo0 + b, std::min(nb, n - b)});
+        ctr_sliced<T>(E, alpha, sa, A, sb, B, (summed && b > 0) ? T(1) : beta, sc, C, s2, budget);
+    }
+}
+
+template void ctr_sliced<double>(Engine&, double, const char*, const double*, const char*,
+                                 const double*, double, const char*, double*,
+                                 const std::vector<Slice>&, long long);
 
 template void ctr<double>(Engine&, double, const char*, const double*, const char*, const double*,
                           double, const char*, double*);

@@ -124,6 +124,7 @@ void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx, in
     }
     using A = typename AccOf<T>::type;
     for (long long s0 = 0; s0 < V; s0 += ts) {
+        c->phase("particle-particle term: group starting at virtual", s0, V);
         const long long ns = std::min(ts, V - s0), nbs = V - s0;
         for (long long a0 = s0; a0 < s0 + ns; a0 += ta) {
             const long long na = std::min(ta, s0 + ns - a0), nb = V - a0;
