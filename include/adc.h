@@ -121,8 +121,9 @@ int adc_set_setup_option(const char* key, double value);
  *                 assembled (3 if its sweeps do not converge), 3 = rocSOLVER
  *                 divide and conquer
  *   "pp_slab_mb"  size bound in MiB of the rebuilt four-virtual slab of the
- *                 particle-particle term (default 16384); a smaller slab means
- *                 more, smaller rebuild blocks
+ *                 particle-particle term (default: the larger of 16 GiB and a
+ *                 third of the device memory free for it, at most 64 GiB); a
+ *                 smaller slab means more, smaller rebuild blocks
  *   "pp_blocks"   minimum number of blocks of a in that rebuild (default 0:
  *                 min(24, V/8) in FP64 and FP32, min(12, V/8) in BF16);
  *                 block k rebuilds only the pairs b >= its first a, so more
@@ -152,6 +153,12 @@ int adc_set_setup_option(const char* key, double value);
  *                 memory, else 2 (default)
  *   "ctr_log"     1 = time each generic contraction with HIP events and
  *                 print its product shape on stderr (sigma then runs eagerly)
+ *   "bvv_host"    EA only.  1 = keep the vv block of the DF factors (V^2 Naux,
+ *                 the largest input tensor) and its FP32 / BF16 copies in
+ *                 pinned host memory instead of the device (the out-of-core
+ *                 storage mode of Sec. III.A): every sigma product that reads
+ *                 it stages the rows it needs, one block at a time; 0 = back
+ *                 on the device (default).  Needs ea_layout -1, 1 or 2
  *   "gemm_config" -1 = tile configuration of each matrix-core product chosen
  *                 by the autotuner or heuristic (default); 0..7 = that
  *                 configuration forced on every product of this context (ids
@@ -280,16 +287,24 @@ int adc_workspace(const adc_ctx* ctx, long long* used, long long* peak);
  *              stream of its own when the context uses the null stream, so
  *              that the host work of one solve overlaps the device work of
  *              the others;
+ *   bit 2 (4): stats has 5 entries (see below);
  *   bits 8-15: number of those threads, 1..64 (0: 8).
  * Without bit 1 the solvers advance in lockstep and each iteration applies
- * sigma to the new trial vectors of every active system, issued back to back
- * over a few default-priority streams.  Results equal those of adc_davidson
- * on each context.
+ * sigma to the new trial vectors of every active system; with bit 0 as one
+ * launch of a graph holding every ready system's sigma graph as a child node
+ * (with the copies of its vectors in and out; independent branches, so the
+ * systems run side by side; instantiated again only when the set of systems,
+ * vector counts or precisions changes), a system whose graph is not yet
+ * captured running its own sigma (and capture) over a few default-priority
+ * streams.  Results equal those of adc_davidson on each context.
  * energies, spec_factors: host [nsys][nroots] (spec_factors may be NULL);
  * n_iter, status: host [nsys] (may be NULL; status per system as
  * adc_davidson returns it; the message of a failed system is its context's
- * adc_last_error); stats: host [3] or NULL: lockstep iterations (concurrent:
- * the largest iteration count), sigma graph replays, graph captures.
+ * adc_last_error); stats: host [3] (or [5] with flag bit 2) or NULL: lockstep
+ * iterations (concurrent: the largest iteration count), sigma graph replays
+ * (one per system and iteration), graph captures; then launches of the
+ * combined graph and the number of times it was instantiated (lockstep with
+ * graphs only; 0 otherwise).
  * Returns ADC_OK when every system converged, else the first non-OK status;
  * ADC_E_ARG for bad arguments (message in adc_last_error(NULL)). */
 int adc_batch_davidson(adc_ctx* const* ctxs, int nsys, int nroots, int flags,

@@ -136,8 +136,8 @@ def batch_davidson(contexts, nroots, use_graph=True, concurrent=False, threads=0
     P = np.zeros((n, nroots))
     it = np.zeros(n, dtype=np.int32)
     st = np.zeros(n, dtype=np.int32)
-    stats = np.zeros(3, dtype=np.int64)
-    flags = int(bool(use_graph)) | (2 if concurrent else 0) | (int(threads) << 8)
+    stats = np.zeros(5, dtype=np.int64)
+    flags = int(bool(use_graph)) | (2 if concurrent else 0) | 4 | (int(threads) << 8)
     rc = lib.adc_batch_davidson(arr, n, int(nroots), flags,
                                 e.ctypes.data_as(ctypes.c_void_p), P.ctypes.data_as(ctypes.c_void_p),
                                 it.ctypes.data_as(ctypes.c_void_p), st.ctypes.data_as(ctypes.c_void_p),
@@ -145,7 +145,8 @@ def batch_davidson(contexts, nroots, use_graph=True, concurrent=False, threads=0
     if rc not in (ADC_OK, ADC_E_NOCONV):
         raise ADCError(rc, last_error(None))
     return e, P, it, st, {"iterations": int(stats[0]), "graph_launches": int(stats[1]),
-                          "captures": int(stats[2])}
+                          "captures": int(stats[2]), "launches": int(stats[3]),
+                          "instantiations": int(stats[4])}
 
 
 def gemm_configs(dtype):

@@ -138,6 +138,10 @@ struct Scratch {
         return true;
     }
     void erase(int slot) { slots.erase(slot); }
+    size_t size_of(int slot) const {
+        auto it = slots.find(slot);
+        return it == slots.end() ? 0 : it->second.bytes();
+    }
     void clear() { slots.clear(); }
 };
 

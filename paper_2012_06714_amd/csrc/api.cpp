@@ -179,6 +179,14 @@ int adc_set_option(adc_ctx* c, const char* key, double value) {
         // 1: time each contraction of sigma with events and print its plan on stderr
         if (value != 0 && value != 1) return fail(c, ADC_E_ARG, "ctr_log: 0 or 1");
         c->E.ctr_log = value == 1;
+    } else if (k == "bvv_host") {
+        // 1: B_vv (and its reduced-precision copies) in pinned host memory, staged per product
+        if (value != 0 && value != 1) return fail(c, ADC_E_ARG, "bvv_host: 0 or 1");
+        if (c->kind != ADC_EA) return fail(c, ADC_E_ARG, "bvv_host: EA contexts only");
+        return guarded(c, [&]() {
+            adc::bvv_set_host(c, value == 1);
+            return ADC_OK;
+        });
     } else if (k == "gemm_config") {
         // force one matrix-core tile configuration on every product (-1: automatic)
         if (value < -1 || value > 7 || value != std::floor(value))
@@ -188,6 +196,7 @@ int adc_set_option(adc_ctx* c, const char* key, double value) {
     } else if (k == "pp_slab_mb") {
         if (value < 1 || value > 1048576) return fail(c, ADC_E_ARG, "pp_slab_mb out of range");
         c->pp_slab_bytes = (long long)(value * 1048576.0);
+        c->pp_slab_set = true;
         c->E.scratch.erase(30);
     } else if (k == "workspace_limit") {
         if (value <= 0) return fail(c, ADC_E_ARG, "workspace_limit must be > 0");
@@ -577,7 +586,7 @@ int adc_batch_davidson(adc_ctx* const* ctxs, int nsys, int nroots, int flags,
                        double* energies, double* spec_factors, int* n_iter, int* status,
                        long long* stats) {
     // bits 0-1: graph, concurrent; bits 8-15: host threads of the concurrent mode
-    if (!ctxs || nsys < 1 || nroots < 1 || !energies || flags < 0 || (flags & ~0xFF03) != 0)
+    if (!ctxs || nsys < 1 || nroots < 1 || !energies || flags < 0 || (flags & ~0xFF07) != 0)
         return fail(nullptr, ADC_E_ARG, "adc_batch_davidson: bad arguments");
     const int nthreads = ((flags >> 8) & 0xFF) ? ((flags >> 8) & 0xFF) : 8;
     if (nthreads > 64) return fail(nullptr, ADC_E_ARG, "adc_batch_davidson: at most 64 threads");
@@ -625,6 +634,10 @@ int adc_batch_davidson(adc_ctx* const* ctxs, int nsys, int nroots, int flags,
             stats[0] = st.iterations;
             stats[1] = st.graph_launches;
             stats[2] = st.captures;
+            if (flags & 4) {
+                stats[3] = st.launches;
+                stats[4] = st.parents;
+            }
         }
         return rc;
     });
@@ -688,6 +701,7 @@ void adc_destroy(adc_ctx* c) {
         if (e) (void)hipEventDestroy(e);
     if (c->own_blas && c->E.blas) rocblas_destroy_handle(c->E.blas);
     if (c->ttu_host) (void)hipHostFree(c->ttu_host);
+    adc::bvv_release_host(c);
     delete c;
 }
 

@@ -1,13 +1,17 @@
 // Several independent systems (contexts) solved together: the Davidson
 // solvers advance in lockstep, and each iteration applies sigma to the new
-// trial vectors of every active system as replays of that system's captured
-// sigma graphs (one per vector count and precision, kept by the context),
-// issued back to back over a few streams so that unequal systems run side by
-// side.  Per-system graphs are captured a handful of times per solve; a
-// single graph over the whole active set would have to be captured again
-// whenever any system converges or changes its number of new vectors.
+// trial vectors of every active system with one graph launch: a parent graph
+// holds, for every system whose sigma graph (captured per vector count and
+// precision, kept by the context) is ready, the copy of its trial vectors
+// into the graph's input, that graph as a child node, and the copy of the
+// result out; the systems' branches are independent, so unequal systems run
+// side by side.  The parent is instantiated again only when the set of
+// (system, vector count, precision) changes; otherwise only its copy nodes
+// are pointed at the iteration's vectors.  A system whose graph is not
+// captured yet runs its sigma (and the capture) on its own first.
 #include "context.hpp"
 
+#include <array>
 #include <atomic>
 #include <thread>
 #include <vector>
@@ -61,6 +65,28 @@ struct StreamSwap {
 
 }  // namespace
 
+namespace {
+
+// The parent graph of one iteration's sigma replays (see above)
+struct Parent {
+    std::vector<std::array<long long, 3>> key;   // (system, nvec, precision)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipGraphNode_t> in, out;          // copy nodes per entry
+    ~Parent() { reset(); }
+    void reset() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        in.clear();
+        out.clear();
+        key.clear();
+    }
+};
+
+}  // namespace
+
 int batch_davidson(adc_ctx* const* ctx, int nsys, int nroots, bool use_graph, double* energies,
                    double* P, int* n_iter, int* status, BatchStats* st) {
     std::vector<Solver*> sol(nsys, nullptr);
@@ -73,6 +99,7 @@ int batch_davidson(adc_ctx* const* ctx, int nsys, int nroots, bool use_graph, do
     } cleanup{sol};
     for (int k = 0; k < nsys; ++k) sol[k] = solver_new(ctx[k], nroots);
     Streams S;
+    Parent par;
     std::vector<const double*> X(nsys);
     std::vector<double*> W(nsys);
     std::vector<int> nn(nsys), prec(nsys), active;
@@ -85,13 +112,74 @@ int batch_davidson(adc_ctx* const* ctx, int nsys, int nroots, bool use_graph, do
         if (!use_graph) {
             for (int k : active) sigma(ctx[k], X[k], W[k], nn[k], prec[k]);
         } else {
-            // each active system replays its own sigma graph (captured per
-            // vector count and precision), the systems dealt round-robin to
-            // the branch streams so that unequal ones run side by side; each
-            // branch waits for its system's stream and the system's stream
-            // waits for the branch
-            int b = 0;
+            // systems with a ready graph: one launch of the parent graph
+            std::vector<int> ready, rest;
+            std::vector<std::array<long long, 3>> key;
+            std::vector<hipGraph_t> child;
             for (int k : active) {
+                hipGraph_t g = sigma_graph_ready(ctx[k], nn[k], prec[k]);
+                if (g) {
+                    ready.push_back(k);
+                    key.push_back({k, nn[k], prec[k]});
+                    child.push_back(g);
+                } else {
+                    rest.push_back(k);
+                }
+            }
+            if (!ready.empty()) {
+                if (key != par.key) {
+                    par.reset();
+                    ADC_HIP(hipGraphCreate(&par.graph, 0));
+                    for (size_t r = 0; r < ready.size(); ++r) {
+                        adc_ctx* c = ctx[ready[r]];
+                        const size_t bytes = (size_t)nn[ready[r]] * c->dim * sizeof(double);
+                        hipGraphNode_t a = nullptr, g = nullptr, b = nullptr;
+                        ADC_HIP(hipGraphAddMemcpyNode1D(&a, par.graph, nullptr, 0, c->Xg.p,
+                                                        X[ready[r]], bytes,
+                                                        hipMemcpyDeviceToDevice));
+                        ADC_HIP(hipGraphAddChildGraphNode(&g, par.graph, &a, 1, child[r]));
+                        ADC_HIP(hipGraphAddMemcpyNode1D(&b, par.graph, &g, 1, W[ready[r]],
+                                                        c->Yg.p, bytes,
+                                                        hipMemcpyDeviceToDevice));
+                        par.in.push_back(a);
+                        par.out.push_back(b);
+                    }
+                    ADC_HIP(hipGraphInstantiate(&par.exec, par.graph, nullptr, nullptr, 0));
+                    par.key = key;
+                    if (st) st->parents++;
+                } else {
+                    for (size_t r = 0; r < ready.size(); ++r) {
+                        adc_ctx* c = ctx[ready[r]];
+                        const size_t bytes = (size_t)nn[ready[r]] * c->dim * sizeof(double);
+                        ADC_HIP(hipGraphExecMemcpyNodeSetParams1D(
+                            par.exec, par.in[r], c->Xg.p, X[ready[r]], bytes,
+                            hipMemcpyDeviceToDevice));
+                        ADC_HIP(hipGraphExecMemcpyNodeSetParams1D(
+                            par.exec, par.out[r], W[ready[r]], c->Yg.p, bytes,
+                            hipMemcpyDeviceToDevice));
+                    }
+                }
+                // the launch waits for every ready system's stream, and they for it
+                for (int k : ready) {
+                    ADC_HIP(hipEventRecord(S.sync, ctx[k]->E.stream));
+                    ADC_HIP(hipStreamWaitEvent(S.main, S.sync, 0));
+                }
+                ADC_HIP(hipGraphLaunch(par.exec, S.main));
+                ADC_HIP(hipEventRecord(S.ready, S.main));
+                for (int k : ready) {
+                    ADC_HIP(hipStreamWaitEvent(ctx[k]->E.stream, S.ready, 0));
+                    ctx[k]->graph_launches++;
+                }
+                if (st) {
+                    st->graph_launches += (long long)ready.size();
+                    st->launches++;
+                }
+            }
+            // the others capture (and run) their graph one by one, the systems
+            // dealt round-robin to the branch streams; each branch waits for its
+            // system's stream and the system's stream waits for the branch
+            int b = 0;
+            for (int k : rest) {
                 adc_ctx* c = ctx[k];
                 hipStream_t br = S.br[b++ % NSTREAM];
                 ADC_HIP(hipEventRecord(S.sync, c->E.stream));

@@ -77,8 +77,16 @@ struct adc_ctx {
     // t~ + u~ parked in pinned host memory (the blocked EA path frees device
     // memory for large systems); the spectroscopic amplitudes stream it back
     double* ttu_host = nullptr;
+    // out-of-core B_vv (option "bvv_host", bvv.hip): the vv block of the DF
+    // factors and its FP32 / BF16 copies in pinned host memory
+    bool bvv_host = false;
+    double* hB64 = nullptr;
+    float* hB32 = nullptr;
+    adc::bf16_t* hB16 = nullptr;
     bool big_mixed = false;   // FP32 copies of the O^2 V^2 operands made
     long long pp_slab_bytes = 16LL << 30;  // rebuilt four-index slab (particle-particle term)
+    bool pp_slab_set = false;              // bound given by option pp_slab_mb
+    long long pp_slab_auto = 0;            // default bound chosen from free memory
     int pp_blocks = 0;                     // minimum number of a-blocks of that term (0: automatic)
     int pp_group = 0;                      // blocks per contraction product (0: automatic)
 
@@ -142,13 +150,15 @@ namespace adc {
 void setup_all(adc_ctx* c, const double* eps, const double* B);
 void build_mixed(adc_ctx* c, bool big = true);   // big: also the O^2 V^2 operands
 void ensure_tt(adc_ctx* c);                       // t~ resident again if it was released
+void release_mixed(adc_ctx* c);                   // free the FP32 / BF16 copies
 void setup_adc3(adc_ctx* c, const double* tt, const double* X1);
 
 // sigma.hip
 template <typename T, typename TB>
 void sigma_block(adc_ctx* c, const double* X, double* Y, int nvec);
 
-// vvvv.hip: out[x][a][b] = sum_cd (ac|bd) in[x][c][d], (ac|bd) rebuilt from B_vv.
+// vvvv.hip: out[x][a][b] = sum_cd (ac|bd) in[x][c][d], (ac|bd) rebuilt from B_vv
+// (Bvv null: the rows are staged from the host copy, option "bvv_host").
 // npair > 0 declares nx = npair^2 rows x = i npair + j with
 // in[(i,j)][c][d] = in[(j,i)][d][c] (the caller guarantees it); the mirrored
 // products are then taken from the direct ones instead of being computed.
@@ -157,6 +167,9 @@ void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx, in
 void sigma(adc_ctx* c, const double* X, double* Y, int nvec, int precision);
 void sigma_eager(adc_ctx* c, const double* X, double* Y, int nvec, int precision);  // one block
 void drop_graphs(adc_ctx* c);
+// the captured sigma graph of (nvec, precision) when it can be replayed as it
+// is (reads Xg, writes Yg), else null
+hipGraph_t sigma_graph_ready(adc_ctx* c, int nvec, int precision);
 void sigma_cost(const adc_ctx* c, int nvec, double* total, double* pp);
 
 // ea_layout.hip
@@ -168,6 +181,14 @@ void ea_layout_build(adc_ctx* c, int level);    // make the arranged operands (o
 // D = P2 - 2 P1, Pm = 2 P1 - P2 (storage TB), Dw = D (storage T); null outputs skipped
 template <typename T, typename TB>
 void ea_pairs(Engine& E, const T* Y, int nvec, int O, int V, TB* P1, TB* P2, TB* D, TB* Pm, T* Dw);
+
+// bvv.hip: out-of-core B_vv
+void bvv_set_host(adc_ctx* c, bool on);        // move B_vv to pinned host memory or back
+void bvv_release_host(adc_ctx* c);             // free the host copies (context teardown)
+long long bvv_chunk_rows(const adc_ctx* c, size_t elem);   // rows (a, b) per staged block
+// rows [r0, r0 + n) of B_vv (each Q long) in type T, staged into scratch slot `slot`
+template <typename T>
+const T* bvv_rows(adc_ctx* c, long long r0, long long n, int slot);
 
 // spectrum.hip
 void spectral_function(hipStream_t st, const double* w, int nw, const double* e, const double* P,
@@ -201,6 +222,8 @@ int davidson(adc_ctx* c, int nroots, double* energies, double* P, double* vecs, 
 struct BatchStats {
     long long graph_launches = 0, captures = 0;
     int iterations = 0;
+    long long launches = 0;   // launches of the parent graph (one per iteration at most)
+    long long parents = 0;    // parent graphs instantiated
 };
 int batch_davidson(adc_ctx* const* ctx, int nsys, int nroots, bool use_graph, double* energies,
                    double* P, int* n_iter, int* status, BatchStats* st);

@@ -552,6 +552,7 @@ struct Solver {
             // refinement: the next level (FP32 products after BF16 when asked
             // for, then FP64) rebuilds the space from the Ritz vectors
             stage = (stage == 1 && c->precision == 2) ? 2 : 0;
+            if (stage == 0) release_mixed(c);   // room for the FP64 products
             stall = 0;
             best_mixed_r = INFINITY;
             ADC_HIP(hipMemcpyAsync(d.V.p, d.X.p, (size_t)nbk * dim * sizeof(double),

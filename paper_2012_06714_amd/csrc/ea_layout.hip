@@ -121,7 +121,13 @@ static size_t layout_bytes(const adc_ctx* c, int level) {
 
 bool ea_layout_use(adc_ctx* c, int level) {
     c->eal.mode = 0;
-    if (c->kind != ADC_EA || c->ea_layout == 0) return false;
+    if (c->kind != ADC_EA) return false;
+    if (c->ea_layout == 0) {
+        if (c->bvv_host)
+            throw Error(ADC_E_STATE, "ea_layout 0 reads B_vv on the device: with bvv_host = 1 "
+                                     "use ea_layout -1, 1 or 2");
+        return false;
+    }
     if (c->order == 2 || c->ea_layout == 1 || c->ea_layout == 2) {
         c->eal.mode = c->order == 2 ? 1 : c->ea_layout;
         return true;

@@ -55,7 +55,7 @@ void build_mixed(adc_ctx* c, bool big) {
         narrow(c, c->ooov, c->fooov);
         narrow(c, c->gam, c->fgam);
         if (c->kind == ADC_EA) {
-            narrow(c, c->Bvv, c->hBvv);
+            if (!c->bvv_host) narrow(c, c->Bvv, c->hBvv);
         } else {
             narrow(c, c->oooo, c->foooo);
             narrow(c, c->Om, c->fOm);
@@ -63,8 +63,32 @@ void build_mixed(adc_ctx* c, bool big) {
         }
     }
     // the first-order coupling reads B_vv in both kinds (EA: (ac|Q) products)
-    if (c->kind == ADC_EA) narrow(c, c->Bvv, c->fBvv);
+    if (c->kind == ADC_EA && !c->bvv_host) narrow(c, c->Bvv, c->fBvv);
     c->mixed_ready = true;
+}
+
+}  // namespace adc
+
+namespace adc {
+
+// Free the reduced-precision copies (the solver calls this when it enters its
+// FP64 phase, so that the FP64 particle-particle slab can use the memory);
+// they are made again by the next reduced-precision sigma.
+void release_mixed(adc_ctx* c) {
+    drop_graphs(c);
+    for (DBuf<float>* b : {&c->fBoo, &c->fBov, &c->fBvo, &c->fBvv, &c->fM11, &c->fovov, &c->foovv,
+                           &c->fooov, &c->foooo, &c->ft, &c->ftt, &c->fgam, &c->fOm, &c->fPi,
+                           &c->eal.fG, &c->eal.fH, &c->eal.fBH, &c->eal.fttT1, &c->eal.fttT2,
+                           &c->eal.ftT1, &c->eal.ftD, &c->eal.foovvT, &c->eal.ftT})
+        b->release();
+    for (DBuf<bf16_t>* b : {&c->hBvv, &c->eal.httT1, &c->eal.httT2, &c->eal.htT1, &c->eal.htD,
+                            &c->eal.hoovvT, &c->eal.htT, &c->eal.hovov})
+        b->release();
+    c->mixed_ready = false;
+    c->big_mixed = false;
+    c->eal.ready_mixed = false;
+    c->eal.ready_f32 = false;
+    c->E.scratch.erase(30);   // the slab is sized again from the free memory
 }
 
 }  // namespace adc

@@ -376,7 +376,19 @@ static void sigma_ea_arranged(adc_ctx* c, const T* Y1, const T* Y2, T* S1, T* S2
     ea_pairs<T, TB>(E, Y2, nvec, (int)O, (int)V, P1, P2, (TB*)nullptr, Pm, Dw);
     // 21: sigma_abi = -sum_Q U[a][z][Q] (ib|Q),  U = sum_c Y_c (ac|Q)
     T* U = slot<T>(E, S_U, (size_t)(V * Z * Q));
-    ctr<T>(E, T(1), "zc", Y1, "acQ", v.Bvv, T(0), "azQ", U);
+    const bool host = c->bvv_host;   // B_vv rows staged from host memory per product
+    const long long bvr = host ? std::max<long long>(1, bvv_chunk_rows(c, sizeof(T)) / V) : V;
+    if (!host) {
+        ctr<T>(E, T(1), "zc", Y1, "acQ", v.Bvv, T(0), "azQ", U);
+    } else {
+        for (long long a0 = 0; a0 < V; a0 += bvr) {
+            const long long n = std::min(bvr, V - a0);
+            E.ext.extra['A'] = n;
+            ctr<T>(E, T(1), "zc", Y1, "AcQ", bvv_rows<T>(c, a0 * V, n * V, 72), T(0), "AzQ",
+                   U + a0 * Z * Q);
+        }
+        E.ext.extra.erase('A');
+    }
     const GemmOut S2_zaib = omap(V, OVV, V, V, VV, 1);    // rows (z,a), columns (i,b)
     const GemmOut S2_iazb = omap(V, VV, V, V, OVV, 1);    // rows (i,a), columns (z,b)
     gemm_map<T, T>(E, false, true, V * Z, OV, Q, -1.0, U, Q, v.Bov, Q, 0.0, S2,
@@ -426,8 +438,16 @@ static void sigma_ea_arranged(adc_ctx* c, const T* Y1, const T* Y2, T* S1, T* S2
             gemm_map<TB, T>(E, false, true, Z * V, OV, OV, 1.0, P2, OV, a.ttT2, OV, 1.0, F2, f2map);
         }
         T* W2 = slot<T>(E, A_W2, (size_t)(Z * O * Q));
-        gemm_map<T, T>(E, false, false, Z * O, Q, VV, 1.0, F2, VV, v.Bvv, Q, 0.0, W2,
-                       GemmOut::rowmajor(Q));
+        if (!host)
+            gemm_map<T, T>(E, false, false, Z * O, Q, VV, 1.0, F2, VV, v.Bvv, Q, 0.0, W2,
+                           GemmOut::rowmajor(Q));
+        else
+            for (long long b0 = 0; b0 < V; b0 += bvr) {
+                const long long n = std::min(bvr, V - b0);
+                gemm_map<T, T>(E, false, false, Z * O, Q, n * V, 1.0, F2 + b0 * V, VV,
+                               bvv_rows<T>(c, b0 * V, n * V, 72), Q, b0 == 0 ? 0.0 : 1.0, W2,
+                               GemmOut::rowmajor(Q));
+            }
         gemm_map<T, T>(E, false, true, Z, V, O * Q, 1.0, W2, O * Q, a.Bvo, O * Q, 1.0, S1,
                        GemmOut::rowmajor(V));
         // sigma_abi -= Y_a Gamma_ib
@@ -449,8 +469,16 @@ static void sigma_ea_arranged(adc_ctx* c, const T* Y1, const T* Y2, T* S1, T* S2
         T* Wk = slot<T>(E, A_WK, (size_t)(Z * O * Q));
         ctr<T>(E, T(1), "zc", Y1, "kcQ", v.Bov, T(0), "zkQ", Wk);
         TB* Rp = slot<TB>(E, A_RP, n4);
-        gemm_map<T, TB>(E, false, true, Z * O, VV, Q, 1.0, Wk, Q, v.Bvv, Q, 0.0, Rp,
-                        omap(O, OVV, V, V, OV, 1));
+        if (!host)
+            gemm_map<T, TB>(E, false, true, Z * O, VV, Q, 1.0, Wk, Q, v.Bvv, Q, 0.0, Rp,
+                            omap(O, OVV, V, V, OV, 1));
+        else
+            for (long long a0 = 0; a0 < V; a0 += bvr) {
+                const long long n = std::min(bvr, V - a0);
+                gemm_map<T, TB>(E, false, true, Z * O, n * V, Q, 1.0, Wk, Q,
+                                bvv_rows<T>(c, a0 * V, n * V, 72), Q, 0.0, Rp + a0 * OV,
+                                omap(O, OVV, V, V, OV, 1));
+            }
         if (blocked) {
             blocked_nt<TB, T>(c, false, Z * V, t1, O, 1.0, Rp, OV, 1.0, S2, S2_zaib, VV);
             blocked_nt<TB, T>(c, true, Z * V, tD, O, 1.0, Rp, OV, 1.0, S2, S2_iazb, VV);
@@ -475,8 +503,16 @@ static void sigma_ea_arranged(adc_ctx* c, const T* Y1, const T* Y2, T* S1, T* S2
     // (ADC(2): no H)
     gemm_map<T, T>(E, false, false, Z * V, Q, OV, 1.0, Dw, OV, BW, Q, 0.0, W,
                    GemmOut::rowmajor(Q));
-    gemm_map<T, T>(E, false, true, Z, V, V * Q, 1.0, W, V * Q, v.Bvv, V * Q, 1.0, S1,
-                   GemmOut::rowmajor(V));
+    if (!host)
+        gemm_map<T, T>(E, false, true, Z, V, V * Q, 1.0, W, V * Q, v.Bvv, V * Q, 1.0, S1,
+                       GemmOut::rowmajor(V));
+    else
+        for (long long a0 = 0; a0 < V; a0 += bvr) {
+            const long long n = std::min(bvr, V - a0);
+            gemm_map<T, T>(E, false, true, Z, n, V * Q, 1.0, W, V * Q,
+                           bvv_rows<T>(c, a0 * V, n * V, 72), V * Q, 1.0, S1 + a0,
+                           GemmOut::rowmajor(V));
+        }
 }
 
 template <typename T, typename TB>
@@ -523,7 +559,8 @@ void sigma_block(adc_ctx* c, const double* X, double* Yout, int nvec) {
     double beta2 = 0.0;
     if (ea3) {
         using P = TB;
-        const P* Bvv = level_of<T, TB>() == 0   ? (const P*)c->Bvv.p
+        const P* Bvv = c->bvv_host                ? nullptr   // staged from host memory
+                       : level_of<T, TB>() == 0   ? (const P*)c->Bvv.p
                        : level_of<T, TB>() == 1 ? (const P*)c->hBvv.p
                                                 : (const P*)c->fBvv.p;
         P* Zp = slot<P>(E, S_T4, (size_t)nvec * len2);
@@ -649,6 +686,15 @@ static void sigma_graph(adc_ctx* c, const double* X, double* Y, int nvec, int pr
         ADC_HIP(hipEventRecord(c->gdone, c->gstream));
         ADC_HIP(hipStreamWaitEvent(nullptr, c->gdone, 0));
     }
+}
+
+hipGraph_t sigma_graph_ready(adc_ctx* c, int nvec, int precision) {
+    if (nvec > 64 || !c->Xg.p || c->Xg.n < (size_t)nvec * c->dim) return nullptr;
+    for (auto& g : c->graphs)
+        if (g.nvec == nvec && g.precision == precision && g.exec &&
+            c->E.scratch.still_valid(g.slots))
+            return g.graph;
+    return nullptr;
 }
 
 void sigma(adc_ctx* c, const double* X, double* Y, int nvec, int precision) {

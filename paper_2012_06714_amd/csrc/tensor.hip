@@ -91,9 +91,18 @@ void gemm_run(Engine& E, bool ta, bool tb, long long M, long long N, long long K
               GemmOut out, long long batch, int kind, GemmInner inner) {
     using Acc = typename AccOf<T>::type;
     if (M <= 0 || N <= 0 || batch <= 0 || inner.n <= 0) return;
+    // shapes are tuned per class (each extent rounded up to a power of two):
+    // loops whose products differ only a little in one extent (the particle-
+    // particle groups) reuse one trial instead of timing every shape
+    auto cls = [](long long x) {
+        long long p = 1;
+        while (p < x) p <<= 1;
+        return p;
+    };
     const std::array<long long, 12> key{(long long)sizeof(TI), (long long)sizeof(T),
-                                        (long long)sizeof(TO), ta, tb, M, N, K, batch * inner.n,
-                                        kind, out.rsplit > 0, out.csplit > 0};
+                                        (long long)sizeof(TO), ta, tb, cls(M), cls(N), cls(K),
+                                        cls(batch * inner.n), kind, out.rsplit > 0,
+                                        out.csplit > 0};
     if (E.force_cfg >= 0) {   // a forced tile (configurations not compiled for T run as 0)
         mfma_gemm<TI, T, TO>(E.stream, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,
                              out, batch, kind, E.force_cfg, inner);

@@ -87,7 +87,25 @@ void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx, in
     Engine& E = c->E;
     const long long V = c->V, Q = c->Q, VV = V * V, V3 = VV * V;
     if (nx <= 0) return;
-    long long ta_max = std::max<long long>(1, c->pp_slab_bytes / (long long)(sizeof(T) * V3));
+    // slab bound: the option, or by default the larger of 16 GiB and a third of
+    // the device memory free for it (at most 64 GiB) -- large V needs room for
+    // several values of a per group (V^3 elements each)
+    long long slab_bytes = c->pp_slab_bytes;
+    if (!c->pp_slab_set) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        ADC_HIP(hipStreamIsCapturing(E.stream, &cs));
+        if (cs == hipStreamCaptureStatusNone) {
+            size_t fr = 0, tot = 0;
+            if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+                const long long have = (long long)fr + E.scratch.size_of(30);
+                c->pp_slab_auto = std::max<long long>(16LL << 30, std::min<long long>(64LL << 30, have / 3));
+            } else {
+                (void)hipGetLastError();
+            }
+        }
+        if (c->pp_slab_auto > 0) slab_bytes = c->pp_slab_auto;
+    }
+    long long ta_max = std::max<long long>(1, slab_bytes / (long long)(sizeof(T) * V3));
     ta_max = std::min(ta_max, V);
     // more blocks rebuild fewer mirrored pairs (Naux V^3 (V + na) flops) but
     // make smaller rebuild products: at least pp_blocks of them (default 24
@@ -135,9 +153,22 @@ void vvvv_apply(adc_ctx* c, const T* Bvv, const T* in, TO* out, long long nx, in
             slab.csplit = V;
             slab.cs1 = VV;
             slab.cs2 = 1;
-            const T* Ba = Bvv + a0 * V * Q;
-            gemm_run<T, T, T>(E, false, true, na * V, nb * V, Q, A(1), Ba, Q, 0, Ba, Q, 0, A(0),
-                               K + ((a0 - s0) * nbs + (a0 - s0)) * VV, slab, 1, 1);
+            if (Bvv) {
+                const T* Ba = Bvv + a0 * V * Q;
+                gemm_run<T, T, T>(E, false, true, na * V, nb * V, Q, A(1), Ba, Q, 0, Ba, Q, 0,
+                                  A(0), K + ((a0 - s0) * nbs + (a0 - s0)) * VV, slab, 1, 1);
+            } else {
+                // B_vv in host memory: rows (a, c) of the block, then the columns
+                // (b, d) in staged blocks of b
+                const T* Ba = bvv_rows<T>(c, a0 * V, na * V, 72);
+                const long long nbc = std::max<long long>(1, bvv_chunk_rows(c, sizeof(T)) / V);
+                for (long long b0 = a0; b0 < V; b0 += nbc) {
+                    const long long nbb = std::min(nbc, V - b0);
+                    const T* Bb = bvv_rows<T>(c, b0 * V, nbb * V, 73);
+                    gemm_run<T, T, T>(E, false, true, na * V, nbb * V, Q, A(1), Ba, Q, 0, Bb, Q, 0,
+                                      A(0), K + ((a0 - s0) * nbs + (b0 - s0)) * VV, slab, 1, 1);
+                }
+            }
             E.gemm_flops += 2LL * na * V * nb * V * Q;
         }
         GemmOut pairs;                                     // x x (a, b-s0) -> [x][a][b]

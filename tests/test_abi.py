@@ -45,8 +45,9 @@ def test_host_validation_without_gpu():
     assert used.value == -7 and peak.value == -7
     arr = (ctypes.c_void_p * 1)(8)
     e = (ctypes.c_double * 1)()
-    # flag bits outside graph/concurrent/thread count, and more than 64 threads
-    assert lib.adc_batch_davidson(arr, 1, 1, 4, e, None, None, None, None) == adc.ADC_E_ARG
+    # flag bits outside graph/concurrent/stats/thread count, and more than 64 threads
+    assert lib.adc_batch_davidson(arr, 1, 1, 8, e, None, None, None, None) == adc.ADC_E_ARG
+    assert lib.adc_batch_davidson(arr, 1, 1, 1 << 16, e, None, None, None, None) == adc.ADC_E_ARG
     assert lib.adc_batch_davidson(arr, 1, 1, 2 | (65 << 8), e, None, None, None, None) == adc.ADC_E_ARG
     lib.adc_destroy(None)
     # the batch object: argument checks before any device work

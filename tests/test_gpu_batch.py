@@ -103,6 +103,11 @@ def test_batch_matches_single_solves(precision):
             # (system, vector count, precision), reused across iterations
             assert stats["graph_launches"] == sum(int(i) for i in it)
             assert 1 <= stats["captures"] < stats["graph_launches"]
+            if not concurrent:
+                # lockstep: at most one launch of the combined graph per iteration,
+                # re-instantiated only when the set of systems/vector counts changes
+                assert 1 <= stats["launches"] <= stats["iterations"]
+                assert 1 <= stats["instantiations"] <= stats["launches"]
 
 
 def test_batch_object_matches_oracle():

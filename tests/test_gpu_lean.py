@@ -110,3 +110,49 @@ def test_blocked_ea_sigma_matches_oracle():
         assert np.abs(np.array(e) - w).max() < 1e-8
         assert (np.abs(np.array(Pd) - Pw) / np.maximum(1, np.abs(Pw))).max() < 1e-5
     ctx.close()
+
+
+@pytest.mark.parametrize("order", [3, 2])
+def test_out_of_core_bvv_matches_oracle(order):
+    """Option bvv_host: B_vv and its FP32 / BF16 copies in pinned host memory,
+    staged per product one block of rows at a time (a tiny slice budget makes
+    every block one virtual index), with the blocked and resident EA paths;
+    then moved back to the device."""
+    from oracle.radc import RADC
+    from synthetic import random_vectors, small_system
+    O, V, Q = 4, 24, 60
+    eps, B = small_system(O, V, Q, 81)
+    _say(f"case out-of-core B_vv n={order}")
+    ref = RADC(eps, B, O, order, "ea")
+    X = random_vectors(ref.dim, 3, 82)
+    s_ref = ref.sigma(X)
+    mag = ref.sigma_magnitude(X)
+    ctx = _sliced_ctx(eps, B, O, order, "ea", 100)
+    Xd = torch.tensor(X, device="cuda")
+    s_dev = ctx.sigma(Xd).cpu().numpy()
+    ctx.set_option("bvv_host", 1)
+    for layout in ((1, 2) if order == 3 else (1,)):
+        ctx.set_option("ea_layout", layout)
+        for level in (0, 1, 2):
+            ctx.set_option("precision", level)
+            s = ctx.sigma(Xd).cpu().numpy()
+            if level == 0:
+                err = np.abs(s - s_ref).max() / np.abs(s_ref).max()
+                _say(f"  layout {layout} level 0: {err:.3e}")
+                assert err <= 1e-12
+            else:
+                ratio = float((np.abs(s - s_ref) / (mag + 1e-300)).max())
+                _say(f"  layout {layout} level {level}: {ratio:.3e}")
+                assert ratio <= LEVEL_TOL[level]
+    ctx.set_option("precision", 0)
+    ctx.set_option("tol_e", 1e-10)
+    ctx.set_option("tol_r", 1e-8)
+    e, P, _, it, ok = ctx.davidson(3, want_vectors=False)
+    assert ok
+    from oracle.davidson import davidson
+    w, vec, _, conv = davidson(ref.sigma, ref.diag(), 3, block=6, tol_e=1e-11, tol_r=1e-7)
+    assert conv and np.abs(np.array(e) - w).max() < 1e-8
+    ctx.set_option("bvv_host", 0)
+    s_back = ctx.sigma(Xd).cpu().numpy()
+    assert np.abs(s_back - s_dev).max() <= 1e-13 * np.abs(s_dev).max()
+    ctx.close()
