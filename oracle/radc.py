@@ -157,7 +157,7 @@ class RADC:
         D2 = (ev[None, None, :, None] + ev[None, None, None, :]
               - eo[:, None, None, None] - eo[None, :, None, None])       # e_a+e_b-e_i-e_j
         Bov = self.Bb[("o", "v")]
-        ovov = np.einsum("Qia,Qjb->iajb", Bov, Bov)
+        ovov = _ovov(Bov)
         self.T["t"] = -ovov.transpose(0, 2, 1, 3) / D2                # (ia|jb)/(ei+ej-ea-eb)
         amp = radc_terms.AMP_TERMS
         self.T["s"] = -self._eval(amp["t1_2"], "ia") / D1
@@ -175,8 +175,7 @@ class RADC:
 
     def mp_energy(self, k):
         """k-th order correlation energy: E(2) from t, E(3) from u (closed shell)."""
-        Bov = self.Bb[("o", "v")]
-        ovov = np.einsum("Qia,Qjb->iajb", Bov, Bov)
+        ovov = _ovov(self.Bb[("o", "v")])
         x = self.T["t"] if k == 2 else self.T["u"]
         return float(np.einsum("ijab,iajb->", x, 2 * ovov - ovov.transpose(0, 3, 2, 1)))
 
@@ -254,6 +253,37 @@ class RADC:
         Y2 = self.z_to_y(Z2)
         s1, s2 = self.sigma_y(Z1, Y2, skip_11=skip_11)
         return self.pack(s1, self.y_to_z(s2))
+
+    def sigma_rows(self, vecs, rows):
+        """Selected elements of the 2p1h (EA) / 2h1p (IP) part of sigma = M_Z X,
+        each computed on its own (for systems whose whole sigma is out of reach):
+        rows are (x, p, q) in the boundary layout Z2[x][p][q] (EA: (i, a, b),
+        IP: (a, i, j)).  Every 21 and 22 term of the Y rows is evaluated with
+        its output indices fixed, for the row (p, q, x) and its pair partner
+        (q, p, x), then mapped to the Z basis (the 2x2 pair transform).
+        Returns [nvec, nrows]."""
+        Z1, Z2 = self.unpack(vecs)
+        Y2 = self.z_to_y(Z2)
+        ext = "abi" if self.kind == "ea" else "ija"
+        terms = self._blocks("21") + self._blocks("22")
+        out = np.zeros((Z1.shape[0], len(rows)))
+        for r, (x, p, q) in enumerate(rows):
+            vals = []
+            for (u, w) in ((p, q), (q, p)):
+                fixed = {ext[0]: u, ext[1]: w, ext[2]: x}
+                acc = np.zeros(Z1.shape[0])
+                for coef, spec in terms:
+                    subs, ops = self._operands(spec, Y1=Z1, Y2=Y2)
+                    sops = []
+                    for sub, op in zip(subs, ops):
+                        sl = tuple(slice(fixed[c], fixed[c] + 1) if c in fixed else slice(None)
+                                   for c in sub)
+                        sops.append(op[sl])
+                    val = np.einsum(",".join(subs) + "->z" + ext, *sops, optimize=True)
+                    acc += float(eval_fraction(coef)) * val.reshape(Z1.shape[0])
+                vals.append(acc)
+            out[:, r] = AL * vals[0] + BE * vals[1] if p != q else vals[0]
+        return out
 
     def sigma_magnitude(self, vecs):
         """Scale for rounding-error bounds of sigma, element by element: the
@@ -364,6 +394,13 @@ class RADC:
         """P = 2 sum_p X_p^2 (Eq. 50) for normalised vectors in the Z basis."""
         X = self.spec_amplitudes(vecs)
         return 2.0 * np.sum(X * X, axis=1)
+
+
+def _ovov(Bov):
+    """(ia|jb) = sum_Q B^Q_ia B^Q_jb (Eq. 38) as one matrix product over Q."""
+    Q, O, V = Bov.shape
+    flat = Bov.reshape(Q, O * V)
+    return (flat.T @ flat).reshape(O, V, O, V)
 
 
 # Largest intermediate (elements) a single einsum step may create; bigger terms

@@ -214,3 +214,22 @@ def test_sigma_magnitude_bounds_every_product(kind, order):
     M = r.explicit()
     assert np.all(Mabs >= np.abs(M) - 1e-12 * np.abs(Mabs).max())
     assert np.all(A <= (np.abs(X) @ Mabs.T) * (1 + 1e-12) + 1e-12)
+
+
+@pytest.mark.parametrize("kind", ["ea", "ip"])
+@pytest.mark.parametrize("order", [2, 3])
+def test_sampled_sigma_rows_equal_full_sigma(kind, order):
+    """Elements of the 2p1h / 2h1p rows computed one by one (the check used at
+    sizes whose full oracle sigma is out of reach) equal the full sigma's,
+    diagonal pairs (p = q) and both members of a pair included."""
+    eps, B = small_system(3, 5, 12, 23)
+    r = RADC(eps, B, 3, order, kind)
+    rng = np.random.default_rng(7)
+    X = rng.standard_normal((2, r.dim))
+    S = r.sigma(X)
+    nx, npr = (3, 5) if kind == "ea" else (5, 3)
+    rows = [(0, 0, 0), (1, 2, npr - 1), (1, npr - 1, 2), (nx - 1, npr - 1, 0), (2, 1, 1)]
+    got = r.sigma_rows(X, rows)
+    for k, (x, p, q) in enumerate(rows):
+        idx = r.n1 + (x * npr + p) * npr + q
+        assert np.abs(got[:, k] - S[:, idx]).max() <= 1e-12 * np.abs(S).max()
