@@ -90,6 +90,16 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
  *                   of this size or less, so that the setup's temporaries stay
  *                   bounded; default 0 = 2^28); results do not depend on it
  *                   beyond the order of floating-point sums;
+ *   "m11_onthefly"  1: skip the precomputation of the 1p-1p (EA) / 1h-1h (IP)
+ *                   block (step 3 of Sec. III.A); every sigma applies it to
+ *                   the trial vectors on the fly through intermediates (the
+ *                   alternative the paper describes there: no O^2 V^4 block
+ *                   build, at most O^3 V^2 or V^2 Naux work per vector, in
+ *                   FP64 at every precision level), keeping u, D u, Lambda and
+ *                   the small P intermediates resident.  adc_diag then gives
+ *                   that block's diagonal through second order only (the
+ *                   Davidson correction and guesses use it as it is);
+ *                   0 (default): the block is precomputed;
  *   "verbose"       1: one line on stderr per setup phase and per block of
  *                   its long loops, with the seconds since adc_setup began
  *                   (each line synchronises the stream); 0 (default): silent.
@@ -173,7 +183,8 @@ int adc_set_stream(adc_ctx* ctx, void* hip_stream);
 /* Dimension of the ADC matrix (see the layout above); -1 for NULL. */
 long long adc_dim(const adc_ctx* ctx);
 
-/* Exact diagonal of M in the Z basis (the diagonal that the Davidson
+/* Exact diagonal of M in the Z basis (with the setup option "m11_onthefly":
+ * the 1p-1p / 1h-1h part through second order) (the diagonal that the Davidson
  * correction of Sec. III.A, step 4, divides by; the paper does not say which
  * diagonal its solver uses, and this one is exact: the 1p-1p / 1h-1h block's
  * diagonal through order n and, in the 2p1h / 2h1p block, the zeroth-order

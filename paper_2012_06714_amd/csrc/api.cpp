@@ -14,6 +14,7 @@ thread_local std::string g_err = "no error";
 // setup options of this thread (adc_set_setup_option), applied by adc_setup
 thread_local long long g_slice_budget = 0;
 thread_local int g_setup_verbose = 0;
+thread_local int g_m11_fly = 0;
 
 int fail(adc_ctx* c, int code, const std::string& msg) {
     if (c)
@@ -73,6 +74,7 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux, 
     c->E.scratch.arena = &c->arena;
     if (g_slice_budget > 0) c->E.slice_budget = g_slice_budget;
     c->setup_verbose = g_setup_verbose;
+    c->m11_fly = g_m11_fly != 0;
     c->setup_t0 = std::chrono::steady_clock::now();
     int rc = guarded(nullptr, [&]() {
         ADC_BLAS(rocblas_create_handle(&c->E.blas));
@@ -101,6 +103,11 @@ int adc_set_setup_option(const char* key, double value) {
     if (k == "verbose") {
         if (value != 0 && value != 1) return fail(nullptr, ADC_E_ARG, "verbose: 0 or 1");
         g_setup_verbose = (int)value;
+        return ADC_OK;
+    }
+    if (k == "m11_onthefly") {
+        if (value != 0 && value != 1) return fail(nullptr, ADC_E_ARG, "m11_onthefly: 0 or 1");
+        g_m11_fly = (int)value;
         return ADC_OK;
     }
     return fail(nullptr, ADC_E_ARG, "adc_set_setup_option: unknown key '" + k + "'");

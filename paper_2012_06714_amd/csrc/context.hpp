@@ -40,6 +40,11 @@ struct adc_ctx {
     adc::DBuf<double> rho, om, ttu;     // spectroscopic-amplitude helpers
     adc::DBuf<double> tt;               // t~ = 2 t_ij^ab - t_ij^ba (order 3)
     adc::DBuf<double> Om, Pi;           // IP-ADC(3) precontracted blocks [O][O][O][V]
+    // 1p-1p / 1h-1h block applied on the fly (setup option "m11_onthefly",
+    // m11_fly.hip): M11 then holds only its diagonal through second order, and
+    // the intermediates below stay resident (u also stays for order 3)
+    bool m11_fly = false;
+    adc::DBuf<double> Du, Lam, P, P7, Pt, wq;   // D u, Lambda, P_kl, P7_ijkl, Pt_ce, Pt.(ce|Q)
     adc::DBuf<double> guess;            // warm start
     int nguess = 0;
 
@@ -195,6 +200,9 @@ void spectral_function(hipStream_t st, const double* w, int nw, const double* e,
                        int nr, double eta, double* A);
 void propagator_diag(hipStream_t st, const double* w, int nw, const double* e, const double* X,
                      int nr, int norb, double eta, double* G);
+
+// m11_fly.hip: S1 = M11 Y1 (FP64, [nvec][n1]) from the intermediates, without M11
+void m11_fly(adc_ctx* c, const double* Y1, double* S1, int nvec);
 
 // spec.hip
 void spec_amplitudes(adc_ctx* c, const double* vecs, int nvec, double* Xout /*device [nvec][N]*/);

@@ -535,8 +535,9 @@ struct Solver {
             maxr = std::max(maxr, rnorm[k] / std::max(1.0, std::fabs(theta[k])));
         }
         if (c->verbose) {
-            fprintf(stderr, "adc_davidson it %d m %d nbk %d %s max|dE| %.3e max|r| %.3e theta:", it,
-                    m, nbk, stage == 1 ? "bf16" : stage == 2 ? "fp32" : "fp64", maxde, maxr);
+            fprintf(stderr, "adc_davidson it %d %.2f s m %d nbk %d %s max|dE| %.3e max|r| %.3e theta:",
+                    it, c->hist_t.back(), m, nbk, stage == 1 ? "bf16" : stage == 2 ? "fp32" : "fp64",
+                    maxde, maxr);
             for (int k = 0; k < nbk; ++k) fprintf(stderr, " %.10f(%.1e)", theta[k], rnorm[k]);
             fprintf(stderr, "\n");
         }

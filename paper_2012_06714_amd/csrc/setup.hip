@@ -134,7 +134,28 @@ void setup_all(adc_ctx* c, const double* eps, const double* B) {
     const bool ea = c->kind == ADC_EA;
     const int n1 = c->n1;
     c->M11.alloc((size_t)n1 * n1, &c->arena);
-    {
+    if (c->m11_fly) {
+        // on the fly: M11 keeps only its diagonal through second order,
+        // e_a - tau_aa (EA) or -e_i - kappa_ii (IP), for the Davidson correction
+        Tmp tb;
+        double* td = tb(c, (size_t)n1);
+        if (ea) {
+            ctr_sliced<double>(E, 2.0, "jkca", c->t.p, "jcka", c->ovov.p, 0.0, "a", td);
+            ctr_sliced<double>(E, -1.0, "jkca", c->t.p, "jakc", c->ovov.p, 1.0, "a", td);
+        } else {
+            ctr_sliced<double>(E, 2.0, "ikbc", c->t.p, "ibkc", c->ovov.p, 0.0, "i", td);
+            ctr_sliced<double>(E, -1.0, "ikbc", c->t.p, "ickb", c->ovov.p, 1.0, "i", td);
+        }
+        std::vector<double> h(n1), e(n1), m((size_t)n1 * n1, 0.0);
+        ADC_HIP(hipMemcpyAsync(h.data(), td, n1 * sizeof(double), hipMemcpyDeviceToHost, E.stream));
+        ADC_HIP(hipMemcpyAsync(e.data(), ea ? c->ev.p : c->eo.p, n1 * sizeof(double),
+                               hipMemcpyDeviceToHost, E.stream));
+        ADC_HIP(hipStreamSynchronize(E.stream));
+        for (int a = 0; a < n1; ++a) m[(size_t)a * n1 + a] = (ea ? e[a] : -e[a]) - h[a];
+        ADC_HIP(hipMemcpyAsync(c->M11.p, m.data(), m.size() * sizeof(double),
+                               hipMemcpyHostToDevice, E.stream));
+        ADC_HIP(hipStreamSynchronize(E.stream));
+    } else {
         Tmp tb;
         double* tau = tb(c, (size_t)n1 * n1);
         if (ea) {
@@ -175,7 +196,7 @@ void setup_all(adc_ctx* c, const double* eps, const double* B) {
 
     // ADC(2) needs the (ov|ov) and (oo|ov) blocks only for the amplitudes and
     // M11 above: free them (a batch of systems keeps many contexts resident)
-    if (c->order == 2) {
+    if (c->order == 2 && !c->m11_fly) {   // (the block applied on the fly reads (ov|ov))
         c->ovov.release();
         c->ooov.release();
     }

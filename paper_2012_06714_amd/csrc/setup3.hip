@@ -272,14 +272,18 @@ void setup_adc3(adc_ctx* c, const double* tt, const double* X1) {
 
     c->phase("(oo|vv), (oo|oo), Gamma");
     // ---- shared intermediates ----------------------------------------------------------
-    Buf P_b, P7b, Ptb, wqb;
-    double* P = P_b.get(c, OO);              // P_kl = t_jk^cd t~_lj^dc
+    const bool fly = c->m11_fly;   // the 1p-1p / 1h-1h block is applied on the fly
+    c->P.alloc(OO, &c->arena);
+    double* P = c->P.p;                      // P_kl = t_jk^cd t~_lj^dc
     ctr_sliced<double>(E, 1.0, "jkcd", t, "ljdc", tt, 0.0, "kl", P);
-    double* P7 = P7b.get(c, OO * OO);        // P7_ijkl = t_ij^bc t_kl^cb
+    c->P7.alloc(OO * OO, &c->arena);
+    double* P7 = c->P7.p;                    // P7_ijkl = t_ij^bc t_kl^cb
     ctr_sliced<double>(E, 1.0, "ijbc", t, "klcb", t, 0.0, "ijkl", P7);
-    double* Pt = Ptb.get(c, VV);             // Pt_ce = t_jk^cd t~_kj^de
+    c->Pt.alloc(VV, &c->arena);
+    double* Pt = c->Pt.p;                    // Pt_ce = t_jk^cd t~_kj^de
     ctr_sliced<double>(E, 1.0, "jkcd", t, "kjde", tt, 0.0, "ce", Pt);
-    double* wq = wqb.get(c, (size_t)Q);      // sum_ce Pt_ce B^Q_ce
+    c->wq.alloc((size_t)Q, &c->arena);
+    double* wq = c->wq.p;                    // sum_ce Pt_ce B^Q_ce
     ctr<double>(E, 1.0, "ce", Pt, "ceQ", Bvv, 0.0, "Q", wq);
     {
         // Zp[a][c][Q] = Pt_ce B^Q_ae, one block of a at a time:
@@ -292,11 +296,11 @@ void setup_adc3(adc_ctx* c, const double* tt, const double* X1) {
             const Sl sa{{'a', a0, std::min(na, V - a0)}};
             double* Zv = block_view(Zp, a0, row);
             ctr_sliced<double>(E, 1.0, "aeQ", Bvv, "ce", Pt, 0.0, "acQ", Zv, sa);
-            if (ea) ctr_sliced<double>(E, -1.0, "acQ", Zv, "bcQ", Bvv, 1.0, "ab", M, sa);
+            if (ea && !fly) ctr_sliced<double>(E, -1.0, "acQ", Zv, "bcQ", Bvv, 1.0, "ab", M, sa);
             ctr_sliced<double>(E, -1.0, "ibQ", Bov, "abQ", Zv, 1.0, "ia", R, sa);
         }
     }
-    if (ea) ctr<double>(E, 2.0, "abQ", Bvv, "Q", wq, 1.0, "ab", M);   // 2 Pt.(ce|ab)
+    if (ea && !fly) ctr<double>(E, 2.0, "abQ", Bvv, "Q", wq, 1.0, "ab", M);   // 2 Pt.(ce|ab)
 
     c->phase("P, P7, Pt and the Pt B terms");
     // ---- particle-particle ladder and second-order doubles --------------------------
@@ -309,7 +313,12 @@ void setup_adc3(adc_ctx* c, const double* tt, const double* X1) {
     c->phase("particle-particle ladder");
     // third-order 1p-1p / 1h-1h terms through Lambda~ = 2 Lambda - Lambda^(ab):
     //   EA: - t_jk^cb Lambda~_jk^ca - t_jk^ac Lambda~_jk^bc;  IP: - t_ik^bc Lambda~_jk^bc
-    if (ea) {
+    // (on the fly: Lambda kept instead)
+    if (fly) {
+        c->Lam.alloc(OO * VV, &c->arena);
+        ADC_HIP(hipMemcpyAsync(c->Lam.p, u, OO * VV * sizeof(double), hipMemcpyDeviceToDevice,
+                               E.stream));
+    } else if (ea) {
         ctr_sliced<double>(E, -2.0, "jkcb", t, "jkca", u, 1.0, "ab", M);
         ctr_sliced<double>(E, 1.0, "jkcb", t, "jkac", u, 1.0, "ab", M);
         ctr_sliced<double>(E, -2.0, "jkac", t, "jkbc", u, 1.0, "ab", M);
@@ -331,10 +340,14 @@ void setup_adc3(adc_ctx* c, const double* tt, const double* X1) {
     c->phase("second-order doubles");
 
     // ---- third-order 1p-1p / 1h-1h block -------------------------------------------------
-    if (ea)
+    if (fly) {
+        c->Du.alloc(OO * VV, &c->arena);    // (e_a + e_b - e_i - e_j) u, read on the fly
+        mul_denom2(E, u, c->Du.p, c->eo.p, c->ev.p, O, V);
+    } else if (ea) {
         m11_third_ea(c, M, t, tt, u, P);
-    else
+    } else {
         m11_third_ip(c, M, t, tt, u, P, P7, Pt);
+    }
     E.scratch.clear();
     c->phase("third-order 1p-1p / 1h-1h block");
 
@@ -348,7 +361,7 @@ void setup_adc3(adc_ctx* c, const double* tt, const double* X1) {
     c->ttu.alloc(OO * VV, &c->arena);
     double* ut = c->ttu.p;
     tilde_of(c, u, ut);
-    c->u.release();   // u is read only through u~ from here on
+    if (!fly) c->u.release();   // u is read only through u~ from here on
     {
         Buf x2b;
         double* X2 = x2b.get(c, OV * Q);
@@ -459,6 +472,12 @@ void setup_adc3(adc_ctx* c, const double* tt, const double* X1) {
     }
     // t~ + u~ for the 2p1h / 2h1p part of X
     axpy<double>(E, 1.0, tt, c->ttu.p, OO * VV);
+    if (!fly) {   // the small intermediates are read again only on the fly
+        c->P.release();
+        c->P7.release();
+        c->Pt.release();
+        c->wq.release();
+    }
     E.scratch.clear();
     ADC_HIP(hipStreamSynchronize(E.stream));
 }

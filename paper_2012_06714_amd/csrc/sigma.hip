@@ -56,6 +56,30 @@ static T* slot(Engine& E, int s, size_t n) {
     return (T*)E.scratch.get(s, n * sizeof(T));
 }
 
+// S1 = M11 Y1: the precomputed block, or applied on the fly (FP64)
+template <typename T>
+static void apply_11(adc_ctx* c, const T* M11, const T* Y1, T* S1, int nvec) {
+    Engine& E = c->E;
+    const bool ea = c->kind == ADC_EA;
+    if (!c->m11_fly) {
+        if (ea)
+            ctr<T>(E, T(1), "ab", M11, "zb", Y1, T(0), "za", S1);
+        else
+            ctr<T>(E, T(1), "ij", M11, "zj", Y1, T(0), "zi", S1);
+        return;
+    }
+    if constexpr (sizeof(T) == 8) {
+        m11_fly(c, Y1, S1, nvec);
+    } else {
+        const size_t n = (size_t)nvec * c->n1;
+        double* y = (double*)E.scratch.get(96, n * sizeof(double));
+        double* s = (double*)E.scratch.get(97, n * sizeof(double));
+        convert_f2d(E, Y1, y, n, 0.0);
+        m11_fly(c, y, s, nvec);
+        convert_d2f(E, s, S1, n);
+    }
+}
+
 // first-order coupling, zeroth-order diagonal and the 11 block (ADC(2) and up)
 template <typename T>
 static void sigma_adc2_terms(adc_ctx* c, const Views<T>& v, const T* Y1, const T* Y2, T* S1, T* S2,
@@ -64,8 +88,7 @@ static void sigma_adc2_terms(adc_ctx* c, const Views<T>& v, const T* Y1, const T
     const long long Q = c->Q;
     if (c->kind == ADC_EA) {
         const int V = c->V;
-        // 11 block
-        ctr<T>(E, T(1), "ab", v.M11, "zb", Y1, T(0), "za", S1);
+        apply_11<T>(c, v.M11, Y1, S1, nvec);   // 11 block
         // 12: sigma_a += sum_bcj Y_bcj [(jb|ac) - 2 (jc|ab)]
         T* W = slot<T>(E, S_W, (size_t)nvec * V * Q);
         ctr<T>(E, T(1), "zjbc", Y2, "jbQ", v.Bov, T(0), "zcQ", W);
@@ -79,7 +102,7 @@ static void sigma_adc2_terms(adc_ctx* c, const Views<T>& v, const T* Y1, const T
         zeroth_order<T>(E, Y2, S2, nvec, c->O, V, c->eo.p, c->ev.p, -1.0, 1.0);
     } else {
         const int O = c->O;
-        ctr<T>(E, T(1), "ij", v.M11, "zj", Y1, T(0), "zi", S1);
+        apply_11<T>(c, v.M11, Y1, S1, nvec);   // 11 block
         // 12: sigma_i += sum_jkb Y_jkb [(ki|jb) - 2 (kb|ji)]
         T* W = slot<T>(E, S_W, (size_t)nvec * O * Q);
         ctr<T>(E, T(1), "zbjk", Y2, "bjQ", v.Bvo, T(0), "zkQ", W);
@@ -363,8 +386,7 @@ static void sigma_ea_arranged(adc_ctx* c, const T* Y1, const T* Y2, T* S1, T* S2
     const size_t n4 = (size_t)(Z * OVV);
     const bool o3 = c->order == 3;
 
-    // 11 block
-    ctr<T>(E, T(1), "ab", v.M11, "zb", Y1, T(0), "za", S1);
+    apply_11<T>(c, v.M11, Y1, S1, nvec);   // 11 block
     // pair tensors of the trial vectors
     T* Dw = slot<T>(E, A_DW, n4);
     TB *P1 = nullptr, *P2 = nullptr, *Pm = nullptr;
