@@ -89,6 +89,35 @@ def spin_orbital_tensors(eps, B, nocc, eri=None):
     return eps_so, h_so, g_so
 
 
+def spin_orbital_tensors_u(eps_a, eps_b, B_a, B_b, nocc_a, nocc_b):
+    """Unrestricted (open-shell) reference: spin-orbital eps_P, h_PQ and
+    <PQ|RS> = (pr|qs)_{sP sQ} delta(sP,sR) delta(sQ,sS), where
+    (pq|rs)_{st} = sum_Q B_s^Q_pq B_t^Q_rs (Eq. 38 for each pair of spins).
+
+    Canonical-UHF reading of a synthetic system: each spin's Fock matrix
+    f^s_pq = h^s_pq + sum_t sum_{k occ in t} (pq|kk)_{st} - sum_{k occ in s} (pk|kq)_{ss}
+    is diag(eps_s) by construction, which fixes h^s (the one-electron operator
+    then depends on the spin, as a UHF Fock operator does)."""
+    eps = (np.asarray(eps_a, dtype=np.float64), np.asarray(eps_b, dtype=np.float64))
+    B = (np.asarray(B_a, dtype=np.float64), np.asarray(B_b, dtype=np.float64))
+    nocc = (nocc_a, nocc_b)
+    n = eps[0].size
+    eri = {(s, t): np.einsum("Qpq,Qrs->pqrs", B[s], B[t]) for s in range(2) for t in range(2)}
+    m = 2 * n
+    eps_so = np.zeros(m)
+    h_so = np.zeros((m, m))
+    g_so = np.zeros((m, m, m, m))
+    for s in range(2):
+        eps_so[s::2] = eps[s]
+        J = sum(np.einsum("pqkk->pq", eri[s, t][:, :, :nocc[t], :nocc[t]]) for t in range(2))
+        K = np.einsum("pkkq->pq", eri[s, s][:, :nocc[s], :nocc[s], :])
+        h_so[s::2, s::2] = np.diag(eps[s]) - J + K
+    for s1 in range(2):
+        for s2 in range(2):
+            g_so[s1::2, s2::2, s1::2, s2::2] = eri[s1, s2].transpose(0, 2, 1, 3)
+    return eps_so, h_so, g_so
+
+
 # ---------------------------------------------------------------------------
 # determinant spaces and second-quantised operators
 # ---------------------------------------------------------------------------
@@ -198,9 +227,12 @@ def _coef(S, k, dim):
 # ---------------------------------------------------------------------------
 
 class FockSpaceADC:
-    """EA/IP-ADC(n) matrices of a closed-shell system built in Fock space.
+    """EA/IP-ADC(n) matrices of a closed-shell or (with eps_b, B_b, nocc_b) an
+    open-shell unrestricted reference, built in Fock space.
 
-    Parameters: eps [N], B [Naux, N, N], nocc, order n (2 or 3), kind "ea"/"ip".
+    Parameters: eps [N], B [Naux, N, N], nocc, order n (2 or 3), kind "ea"/"ip";
+    for an unrestricted reference eps, B, nocc are the alpha ones and eps_b,
+    B_b, nocc_b the beta ones.
     Attributes after construction:
       M       spin-orbital ADC matrix (EA: M_+, IP: K = -M_-), symmetric
       T       transition moments [2N, dim]
@@ -210,7 +242,8 @@ class FockSpaceADC:
       amps    {k: {"t1": [2N,2N] array, "t2": {(I,J,A,B): t}}}
     """
 
-    def __init__(self, eps, B, nocc, order, kind, ranks=(1, 2), lam=1.0, eri=None):
+    def __init__(self, eps, B, nocc, order, kind, ranks=(1, 2), lam=1.0, eri=None,
+                 eps_b=None, B_b=None, nocc_b=None):
         self.eps = np.asarray(eps, dtype=np.float64)
         self.B = None if B is None else np.asarray(B, dtype=np.float64) * np.sqrt(lam)
         eri = None if eri is None else np.asarray(eri, dtype=np.float64) * lam
@@ -218,10 +251,20 @@ class FockSpaceADC:
         n = self.eps.size
         self.nmo = n
         self.m = m = 2 * n
-        self.occ = list(range(2 * nocc))
-        self.vir = list(range(2 * nocc, m))
-        self.eps_so, h_so, g_so = spin_orbital_tensors(self.eps, self.B, nocc, eri)
-        nel = 2 * nocc
+        if eps_b is None:
+            # closed shell: spin orbitals 0 .. 2 nocc - 1 occupied
+            self.occ = list(range(2 * nocc))
+            self.vir = list(range(2 * nocc, m))
+            self.eps_so, h_so, g_so = spin_orbital_tensors(self.eps, self.B, nocc, eri)
+        else:
+            # unrestricted reference: nocc alpha (P = 2p, p < nocc) and nocc_b
+            # beta (P = 2p + 1, p < nocc_b) spin orbitals occupied
+            Bb = np.asarray(B_b, dtype=np.float64) * np.sqrt(lam)
+            self.occ = sorted([2 * p for p in range(nocc)] + [2 * p + 1 for p in range(nocc_b)])
+            self.vir = [P for P in range(m) if P not in self.occ]
+            self.eps_so, h_so, g_so = spin_orbital_tensors_u(self.eps, eps_b, self.B, Bb,
+                                                             nocc, nocc_b)
+        nel = len(self.occ)
         self.secN = Sector(m, nel)
         self.secX = Sector(m, nel + 1 if kind == "ea" else nel - 1)
         self.HN = hamiltonian(h_so, g_so, self.secN)

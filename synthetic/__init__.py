@@ -23,6 +23,7 @@ PCG64 ``default_rng``.
 from __future__ import annotations
 
 import dataclasses
+import os
 
 import numpy as np
 
@@ -49,8 +50,10 @@ WORKLOADS = {
     "c1": Workload("ip-adc2-o5v19", "ip", 2, 5, 19, 72, 4, 4, "fp64", 1),
     "c2": Workload("ea-adc3-o20v180", "ea", 3, 20, 180, 600, 8, 16, "fp64", 2),
     "c3": Workload("ea-adc3-o40v460", "ea", 3, 40, 460, 1400, 16, 32, "mixed", 3),
-    "c4ea": Workload("ea-adc3-o60v968", "ea", 3, 60, 968, 3000, 8, 16, "mixed", 4),
-    "c4ip": Workload("ip-adc3-o60v968", "ip", 3, 60, 968, 3000, 8, 16, "mixed", 4),
+    # 1028 orbitals: block 8 (one trial vector per root; a 16-vector BF16 sigma
+    # takes about 11 s here)
+    "c4ea": Workload("ea-adc3-o60v968", "ea", 3, 60, 968, 3000, 8, 8, "mixed", 4),
+    "c4ip": Workload("ip-adc3-o60v968", "ip", 3, 60, 968, 3000, 8, 8, "mixed", 4),
 }
 
 
@@ -69,12 +72,53 @@ def draw_system(nocc: int, nvir: int, naux: int, seed: int,
     eps = np.concatenate([eps_o, eps_v]).astype(np.float64)
     iu, ju = np.triu_indices(n)
     B = np.empty((naux, n, n), dtype=np.float64)
-    for q in range(naux):
-        x = rng.standard_normal(iu.size) * (0.3 * np.exp(-q / 40.0))
+
+    def fill(q, x):
         m = B[q]
         m[iu, ju] = x
         m[ju, iu] = x
+
+    if naux * n * n < (1 << 24):
+        for q in range(naux):
+            fill(q, rng.standard_normal(iu.size) * (0.3 * np.exp(-q / 40.0)))
+        return eps, B
+    # large systems: the draws stay in Q order on this thread (the values are
+    # those of the loop above); the scatter into B runs on worker threads, at
+    # most 2 per worker in flight
+    from concurrent.futures import ThreadPoolExecutor
+    workers = max(1, min(8, len(os.sched_getaffinity(0)) - 1))
+    with ThreadPoolExecutor(workers) as pool:
+        pending = []
+        for q in range(naux):
+            pending.append(pool.submit(fill, q,
+                                       rng.standard_normal(iu.size) * (0.3 * np.exp(-q / 40.0))))
+            if len(pending) > 2 * workers:
+                pending.pop(0).result()
+        for f in pending:
+            f.result()
     return eps, B
+
+
+def draw_system_u(nocc_a: int, nocc_b: int, nmo: int, naux: int, seed: int,
+                  mix: float = 0.05):
+    """Open-shell (unrestricted) system: returns (eps_a, eps_b, B_a, B_b).
+
+    The alpha set is drawn as draw_system(nocc_a, nmo - nocc_a, naux, seed).
+    Then, from the same generator: beta energies (nocc_b occupied ~ U[-2.0,
+    -0.3], nmo - nocc_b virtual ~ U[0.1, 5.0], each sorted) and a rotation
+    U = exp(K) of the orbitals, K antisymmetric with entries ~ N(0, mix^2)
+    above the diagonal; B_b^Q = U^T B_a^Q U (alpha and beta orbitals of an
+    unrestricted reference span the same space but differ)."""
+    from scipy.linalg import expm
+    rng = np.random.default_rng(seed)
+    eps_a, B_a = draw_system(nocc_a, nmo - nocc_a, naux, seed, rng)
+    eps_b = np.concatenate([np.sort(rng.uniform(-2.0, -0.3, size=nocc_b)),
+                            np.sort(rng.uniform(0.1, 5.0, size=nmo - nocc_b))])
+    K = np.triu(rng.standard_normal((nmo, nmo)) * mix, 1)
+    U = expm(K - K.T)
+    B_b = np.einsum("pr,Qpq,qs->Qrs", U, B_a, U, optimize=True)
+    B_b = 0.5 * (B_b + B_b.transpose(0, 2, 1))
+    return eps_a, eps_b, B_a, np.ascontiguousarray(B_b)
 
 
 def draw_batch_sizes(rng: np.random.Generator):

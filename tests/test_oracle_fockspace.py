@@ -96,3 +96,38 @@ def test_mp2_energy_closed_form():
                     iajb, ibja = eri[i, a, j, b], eri[i, b, j, a]
                     e2 += iajb * (2 * iajb - ibja) / (eps[i] + eps[j] - eps[a] - eps[b])
     assert abs(fs.E0[2] - e2) < 1e-13
+
+
+def test_unrestricted_closed_shell_limit():
+    """Beta set equal to the alpha set: the unrestricted construction gives the
+    closed-shell matrices exactly."""
+    eps, B = small_system(2, 3, 8, seed=5)
+    for kind in ("ea", "ip"):
+        a = FockSpaceADC(eps, B, 2, 3, kind)
+        b = FockSpaceADC(eps, B, 2, 3, kind, eps_b=eps, B_b=B, nocc_b=2)
+        assert a.labels == b.labels
+        assert np.abs(a.M - b.M).max() < 1e-12
+        assert np.abs(a.T - b.T).max() < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["ea", "ip"])
+@pytest.mark.parametrize("order", [2, 3])
+def test_unrestricted_error_order_against_full_ci(kind, order):
+    """Open-shell doublet (2 alpha, 1 beta electrons in 4 orbitals): ADC(n)
+    energies and the main state's strength differ from full CI by
+    O(lam^(n+1)), as for the closed shell."""
+    from synthetic import draw_system_u
+    ea, eb, Ba, Bb = draw_system_u(2, 1, 4, 8, seed=6)
+    errs = []
+    for lam in (0.02, 0.01):
+        fs = FockSpaceADC(ea, Ba, 2, order, kind, lam=lam, eps_b=eb, B_b=Bb, nocc_b=1)
+        assert np.abs(fs.M - fs.M.T).max() < 1e-13
+        w, v = np.linalg.eigh(fs.M)
+        P_adc = np.sum((fs.T @ v[:, :1]) ** 2)
+        om, e0, P = _exact(fs, kind, nstate=1)
+        errs.append((w[0] - om, sum(fs.E0) - e0, P_adc - P))
+    expect = 2.0 ** (order + 1)
+    for q in range(3):
+        ratio = errs[0][q] / errs[1][q]
+        assert abs(ratio - expect) < 0.15 * expect, (q, ratio, errs)
+    assert abs(errs[1][0]) < 1e-6
