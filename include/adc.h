@@ -83,6 +83,37 @@ enum {
 int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux,
               int order, int kind, adc_ctx** out);
 
+/* Unrestricted (open-shell) reference: the paper's UADC code (Sec. II; the
+ * open-shell radical of Sec. V.B), EA/IP-ADC(2).  Inputs per spin: orbital
+ * energies eps_a, eps_b ([nmo] each, occupied first, each block ascending)
+ * and density-fitting factors B_a, B_b ([naux][nmo][nmo], symmetric in the
+ * orbital pair; (pq|rs) for spins s, t is sum_Q B_s^Q_pq B_t^Q_rs, Eq. 38),
+ * device or host memory (host inputs are copied to the device whole);
+ * nocc_a alpha and nocc_b beta electrons occupy the lowest orbitals of
+ * their spin, whose Fock matrices are diag(eps_s).  order must be 2.
+ * Setup (FP64): first-order doubles of the three spin blocks, second-order
+ * singles, the 1p-1p (EA) or 1h-1h (IP) block of each spin through second
+ * order, and the exact diagonal.
+ * Vectors hold both spin sectors (the matrix is block diagonal in them),
+ * dim = n1 + the four 2p1h (EA) / 2h1p (IP) blocks, in this order:
+ *   EA: Y alpha [Va], Y beta [Vb], (i a b) spins aaa [Oa][a<b], bab
+ *       [Ob][Va][Vb], aab [Oa][Va][Vb], bbb [Ob][a<b];
+ *   IP: Y alpha [Oa], Y beta [Ob], (a i j) spins aaa [Va][i<j], bab
+ *       [Vb][Oa][Ob], aab [Va][Oa][Ob], bbb [Vb][i<j];
+ * (Va = nmo - nocc_a, Vb = nmo - nocc_b; packed pairs p < q row-major).  The
+ * element of a block is the coefficient of a_b^+ a_a^+ a_i |Phi> (EA) or
+ * a_a^+ a_j a_i |Phi> (IP) with the two like indices in that order (in the
+ * mixed blocks the alpha one first).  The other entry points then work on
+ * the context as on a closed-shell one, with these differences: sigma runs
+ * in FP64 at every precision level; adc_spec_factors and the solver's
+ * factors are P = sum_p X_p^2 over the 2 nmo spin orbitals (Eq. 17; X rows:
+ * alpha orbitals, then beta) instead of the spin-adapted Eq. 50; the
+ * learned preconditioner and its training records are not available
+ * (ADC_E_STATE).  Errors: ADC_E_ARG (NULL pointer, nocc_a or nocc_b outside
+ * [1, nmo), naux < 1, order != 2, bad kind), ADC_E_OOM, ADC_E_HIP. */
+int adc_setup_u(const double* eps_a, const double* eps_b, const double* B_a, const double* B_b,
+                int nocc_a, int nocc_b, int nmo, int naux, int order, int kind, adc_ctx** out);
+
 /* Options taken by later adc_setup calls of the calling thread (the setup
  * runs before any adc_set_option can reach the context):
  *   "slice_budget"  elements per operand slice of the setup's large
@@ -208,7 +239,8 @@ int adc_sigma(adc_ctx* ctx, const double* X, double* Y, int nvec);
  * below the FP64 resolution of theta are rounding) and has residual norm
  * <= tol_r max(1, |theta|).
  * energies, spec_factors: host [nroots] (written; spec_factors may be NULL);
- * P = 2 sum_p |X_p|^2 (Eq. 50, the sum over both spin components).
+ * P = 2 sum_p |X_p|^2 (Eq. 50, the sum over both spin components;
+ * unrestricted contexts: the sum over spin orbitals, see adc_spec_factors).
  * vecs: device [nroots][dim] (written) or NULL.  n_iter: host, may be NULL.
  * Returns ADC_OK, ADC_E_NOCONV (estimates written), or an error. */
 int adc_davidson(adc_ctx* ctx, int nroots, double* energies, double* spec_factors,
@@ -217,7 +249,9 @@ int adc_davidson(adc_ctx* ctx, int nroots, double* energies, double* spec_factor
 /* Spectroscopic factors P = 2 sum_p X_p^2 with X = T Y (Eqs. 16, 46-50)
  * for normalised Z-basis vectors.  vecs: device [nvec][dim];
  * P: host [nvec].  X (optional, device [nvec][N], may be NULL) receives
- * the spectroscopic amplitudes X_p (occupied orbitals first). */
+ * the spectroscopic amplitudes X_p (occupied orbitals first).  Unrestricted
+ * contexts (adc_setup_u): X is [nvec][2N] (alpha orbitals, then beta) and
+ * P = sum_p X_p^2 over those 2N spin orbitals. */
 int adc_spec_factors(adc_ctx* ctx, const double* vecs, int nvec, double* P, double* X);
 
 /* Spectra from the solver's outputs (no context; device pointers on

@@ -34,8 +34,8 @@ construction of oracle/fockspace.py, which uses no derived equation):
     K_JKA,JKA  = e_A - e_J - e_K
     T_pI       = d_pI - 1/4 sum_KCD t_pK^CD t_IK^CD  (p occupied);  -t_I^p (p virtual)
     T_p,JKA    = -t_JK^Ap (p virtual; 0 for p occupied)
-Spectroscopic factors P = sum_p |X_p|^2 over spin orbitals (Eq. 50 without
-the closed-shell factor 2), X = T Y (Eq. 16).
+Spectroscopic factors P = sum_p |X_p|^2 over spin orbitals (Eq. 17), X = T Y
+(Eq. 16).
 
 Vector layout at the library boundary (both spin sectors in one vector; the
 matrix is block diagonal in them):

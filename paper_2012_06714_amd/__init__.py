@@ -27,7 +27,7 @@ ABI_SYMBOLS = ("adc_setup", "adc_set_option", "adc_set_stream", "adc_dim", "adc_
                "adc_batch_davidson", "adc_setup_batch", "adc_batch_set_option",
                "adc_davidson_batch", "adc_batch_context", "adc_batch_destroy", "adc_gemm",
                "adc_gemm_configs", "adc_mlp_forward_noalloc", "adc_set_setup_option",
-               "adc_spectral_function", "adc_propagator_diag")
+               "adc_spectral_function", "adc_propagator_diag", "adc_setup_u")
 
 
 class ADCError(RuntimeError):
@@ -43,6 +43,7 @@ def _load():
     vp, i, d, ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
     sig = {
         "adc_setup": (i, [vp, vp, i, i, i, i, i, ctypes.POINTER(vp)]),
+        "adc_setup_u": (i, [vp, vp, vp, vp, i, i, i, i, i, i, ctypes.POINTER(vp)]),
         "adc_set_option": (i, [vp, ctypes.c_char_p, d]),
         "adc_set_stream": (i, [vp, vp]),
         "adc_dim": (ll, [vp]),
@@ -487,3 +488,32 @@ class Context:
 
     def __exit__(self, *a):
         self.close()
+
+
+class ContextU(Context):
+    """An unrestricted (open-shell) EA/IP-ADC(2) problem (adc_setup_u).
+
+    eps_a, eps_b: [N]; B_a, B_b: [Naux, N, N], float64, on the GPU or in host
+    memory; nocc_a / nocc_b alpha / beta electrons.  Vectors hold both spin
+    sectors (layout in include/adc.h); spectroscopic amplitudes have 2N rows
+    (alpha orbitals, then beta) and the factors are sum |X|^2 over them."""
+
+    def __init__(self, eps_a, eps_b, B_a, B_b, nocc_a, nocc_b, order=2, kind="ea", stream=None):
+        import torch
+        self._torch = torch
+        self.nocc, self.nocc_b = int(nocc_a), int(nocc_b)
+        n = int(eps_a.shape[0])
+        self.nvir = n - self.nocc
+        self.naux = int(B_a.shape[0])
+        self.order, self.kind = int(order), kind
+        h = ctypes.c_void_p()
+        k = ADC_EA if kind == "ea" else ADC_IP if kind == "ip" else -9
+        rc = lib.adc_setup_u(_dev_or_host(eps_a, torch), _dev_or_host(eps_b, torch),
+                             _dev_or_host(B_a, torch), _dev_or_host(B_b, torch), self.nocc,
+                             self.nocc_b, n, self.naux, self.order, k, ctypes.byref(h))
+        _check(rc)
+        self._h = h
+        self.dim = int(lib.adc_dim(h))
+        self.nmo = 2 * n          # rows of the spectroscopic amplitudes
+        if stream is not None:
+            self.set_stream(stream)

@@ -91,6 +91,74 @@ int adc_setup(const double* eps, const double* B, int nocc, int nvir, int naux, 
     return ADC_OK;
 }
 
+int adc_setup_u(const double* eps_a, const double* eps_b, const double* B_a, const double* B_b,
+                int nocc_a, int nocc_b, int nmo, int naux, int order, int kind, adc_ctx** out) {
+    if (!out) return fail(nullptr, ADC_E_ARG, "adc_setup_u: out is NULL");
+    *out = nullptr;
+    if (!eps_a || !eps_b || !B_a || !B_b)
+        return fail(nullptr, ADC_E_ARG, "adc_setup_u: eps_a, eps_b, B_a or B_b is NULL");
+    if (nocc_a < 1 || nocc_b < 1 || naux < 1 || nocc_a >= nmo || nocc_b >= nmo)
+        return fail(nullptr, ADC_E_ARG,
+                    "adc_setup_u: need 1 <= nocc_a, nocc_b < nmo and naux >= 1");
+    if (order != 2)
+        return fail(nullptr, ADC_E_ARG, "adc_setup_u: the unrestricted path is built for order 2");
+    if (kind != ADC_IP && kind != ADC_EA)
+        return fail(nullptr, ADC_E_ARG, "adc_setup_u: kind must be ADC_IP or ADC_EA");
+    if (nmo > 46340) return fail(nullptr, ADC_E_ARG, "adc_setup_u: nmo too large");
+    adc_ctx* c = new (std::nothrow) adc_ctx;
+    if (!c) return fail(nullptr, ADC_E_OOM, "adc_setup_u: host allocation failed");
+    c->uhf = true;
+    auto& u = c->uh;
+    u.Oa = nocc_a;
+    u.Ob = nocc_b;
+    u.Va = nmo - nocc_a;
+    u.Vb = nmo - nocc_b;
+    c->O = u.Oa;
+    c->V = u.Va;
+    c->Q = naux;
+    c->N = nmo;
+    c->order = 2;
+    c->kind = kind;
+    const long long Oa = u.Oa, Ob = u.Ob, Va = u.Va, Vb = u.Vb;
+    long long len[6];
+    if (kind == ADC_EA) {
+        len[0] = Va;
+        len[1] = Vb;
+        len[2] = Oa * (Va * (Va - 1) / 2);
+        len[3] = Ob * Va * Vb;
+        len[4] = Oa * Va * Vb;
+        len[5] = Ob * (Vb * (Vb - 1) / 2);
+    } else {
+        len[0] = Oa;
+        len[1] = Ob;
+        len[2] = Va * (Oa * (Oa - 1) / 2);
+        len[3] = Vb * Oa * Ob;
+        len[4] = Va * Oa * Ob;
+        len[5] = Vb * (Ob * (Ob - 1) / 2);
+    }
+    u.off[0] = 0;
+    for (int k = 0; k < 6; ++k) u.off[k + 1] = u.off[k] + len[k];
+    c->dim = u.off[6];
+    c->n1 = (int)(len[0] + len[1]);
+    c->E.scratch.arena = &c->arena;
+    if (g_slice_budget > 0) c->E.slice_budget = g_slice_budget;
+    c->setup_verbose = g_setup_verbose;
+    c->setup_t0 = std::chrono::steady_clock::now();
+    int rc = guarded(nullptr, [&]() {
+        ADC_BLAS(rocblas_create_handle(&c->E.blas));
+        c->own_blas = true;
+        ADC_BLAS(rocblas_set_stream(c->E.blas, c->E.stream));
+        adc::setup_uhf(c, eps_a, eps_b, B_a, B_b);
+        return ADC_OK;
+    });
+    if (rc != ADC_OK) {
+        adc_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return ADC_OK;
+}
+
 int adc_set_setup_option(const char* key, double value) {
     if (!key) return fail(nullptr, ADC_E_ARG, "adc_set_setup_option: NULL key");
     std::string k(key);
@@ -152,10 +220,14 @@ int adc_set_option(adc_ctx* c, const char* key, double value) {
     } else if (k == "record") {
         // Davidson iterates (Ritz vector, residual, value) kept for training pairs
         if (value < 0 || value > 100000) return fail(c, ADC_E_ARG, "record out of range");
+        if (value > 0 && c->uhf)
+            return fail(c, ADC_E_STATE, "record: training pairs are for closed-shell contexts");
         c->record_max = (int)value;
     } else if (k == "precond") {
         // 0: diagonal; 1: the installed learned correction (adc_precond_mlp)
         if (value != 0 && value != 1) return fail(c, ADC_E_ARG, "precond: 0 or 1");
+        if (value == 1 && c->uhf)
+            return fail(c, ADC_E_STATE, "precond: the learned correction is for closed-shell contexts");
         if (value == 1 && !c->mlp_params.p)
             return fail(c, ADC_E_STATE, "precond: no network installed (adc_precond_mlp)");
         c->use_mlp = value == 1;
@@ -189,7 +261,8 @@ int adc_set_option(adc_ctx* c, const char* key, double value) {
     } else if (k == "bvv_host") {
         // 1: B_vv (and its reduced-precision copies) in pinned host memory, staged per product
         if (value != 0 && value != 1) return fail(c, ADC_E_ARG, "bvv_host: 0 or 1");
-        if (c->kind != ADC_EA) return fail(c, ADC_E_ARG, "bvv_host: EA contexts only");
+        if (c->kind != ADC_EA || c->uhf)
+            return fail(c, ADC_E_ARG, "bvv_host: closed-shell EA contexts only");
         return guarded(c, [&]() {
             adc::bvv_set_host(c, value == 1);
             return ADC_OK;
@@ -267,18 +340,19 @@ int adc_spec_factors(adc_ctx* c, const double* vecs, int nvec, double* P, double
         adc::DBuf<double> Xs;
         double* Xd = X;
         if (!Xd) {
-            Xs.alloc((size_t)nvec * c->N, &c->arena);
+            Xs.alloc((size_t)nvec * c->nspec(), &c->arena);
             Xd = Xs.p;
         }
         adc::spec_amplitudes(c, vecs, nvec, Xd);
-        std::vector<double> xh((size_t)nvec * c->N);
+        std::vector<double> xh((size_t)nvec * c->nspec());
         ADC_HIP(hipMemcpyAsync(xh.data(), Xd, xh.size() * sizeof(double), hipMemcpyDeviceToHost,
                                c->E.stream));
         ADC_HIP(hipStreamSynchronize(c->E.stream));
         for (int k = 0; k < nvec; ++k) {
             double s = 0.0;
-            for (int p = 0; p < c->N; ++p) s += xh[(size_t)k * c->N + p] * xh[(size_t)k * c->N + p];
-            P[k] = 2.0 * s;
+            const int ns = c->nspec();
+            for (int p = 0; p < ns; ++p) s += xh[(size_t)k * ns + p] * xh[(size_t)k * ns + p];
+            P[k] = c->spec_scale() * s;
         }
         return ADC_OK;
     });
@@ -476,6 +550,7 @@ int adc_mlp_pairs(adc_ctx* c, const double* x, const double* r, double theta, co
     if (!c) return fail(nullptr, ADC_E_ARG, "adc_mlp_pairs: NULL context");
     if (!x || !r || !xstar || !idx || !F || !a || !t || nidx < 1 || !std::isfinite(theta))
         return fail(c, ADC_E_ARG, "adc_mlp_pairs: bad arguments");
+    if (c->uhf) return fail(c, ADC_E_STATE, "adc_mlp_pairs: closed-shell contexts only");
     return guarded(c, [&]() {
         adc::mlp_pairs(c, x, r, theta, xstar, idx, nidx, F, a, t);
         ADC_HIP(hipStreamSynchronize(c->E.stream));

@@ -45,6 +45,20 @@ struct adc_ctx {
     // the intermediates below stay resident (u also stays for order 3)
     bool m11_fly = false;
     adc::DBuf<double> Du, Lam, P, P7, Pt, wq;   // D u, Lambda, P_kl, P7_ijkl, Pt_ce, Pt.(ce|Q)
+    // unrestricted (open-shell) reference, uadc.hip: O, V above are the alpha
+    // counts; the spin blocks live here
+    bool uhf = false;
+    struct Uhf {
+        int Oa = 0, Ob = 0, Va = 0, Vb = 0;
+        long long off[7] = {0, 0, 0, 0, 0, 0, 0};   // Y1a Y1b aaa bab aab bbb | end
+        adc::DBuf<double> eoa, eva, eob, evb;
+        adc::DBuf<double> Booa, Bova, Bvva, Boob, Bovb, Bvvb;
+        adc::DBuf<double> taa, tab, tbb, t1a, t1b, M11a, M11b, rhoa, rhob;
+    } uh;
+    // spectroscopic amplitudes per vector: N spatial orbitals (closed shell,
+    // Eq. 50 carries the factor 2 of the two spins) or 2N spin orbitals
+    int nspec() const { return uhf ? 2 * N : N; }
+    double spec_scale() const { return uhf ? 1.0 : 2.0; }
     adc::DBuf<double> guess;            // warm start
     int nguess = 0;
 
@@ -205,7 +219,15 @@ void propagator_diag(hipStream_t st, const double* w, int nw, const double* e, c
 void m11_fly(adc_ctx* c, const double* Y1, double* S1, int nvec);
 
 // spec.hip
-void spec_amplitudes(adc_ctx* c, const double* vecs, int nvec, double* Xout /*device [nvec][N]*/);
+void spec_amplitudes(adc_ctx* c, const double* vecs, int nvec,
+                     double* Xout /*device [nvec][c->nspec()]*/);
+
+// uadc.hip: unrestricted EA/IP-ADC(2)
+void setup_uhf(adc_ctx* c, const double* eps_a, const double* eps_b, const double* B_a,
+               const double* B_b);
+void sigma_uhf(adc_ctx* c, const double* X, double* Y, int nvec);   // FP64 at every level
+void spec_amplitudes_uhf(adc_ctx* c, const double* vecs, int nvec, double* Xout);
+void sigma_cost_uhf(const adc_ctx* c, int nvec, double* total);
 
 // mlp.hip: learned preconditioner (layout and features documented there)
 constexpr int MLP_NF = 7, MLP_WIDTH = 256;

@@ -638,17 +638,17 @@ struct Solver {
                                    hipMemcpyDeviceToDevice, E.stream));
         if (P) {
             DBuf<double> Xs;
-            Xs.alloc((size_t)nroots * c->N, &c->arena);
+            Xs.alloc((size_t)nroots * c->nspec(), &c->arena);
             spec_amplitudes(c, d.X.p, nroots, Xs.p);
-            std::vector<double> xh((size_t)nroots * c->N);
+            std::vector<double> xh((size_t)nroots * c->nspec());
             ADC_HIP(hipMemcpyAsync(xh.data(), Xs.p, xh.size() * sizeof(double),
                                    hipMemcpyDeviceToHost, E.stream));
             ADC_HIP(hipStreamSynchronize(E.stream));
             for (int k = 0; k < nroots; ++k) {
                 double s = 0.0;
-                for (int p = 0; p < c->N; ++p)
-                    s += xh[(size_t)k * c->N + p] * xh[(size_t)k * c->N + p];
-                P[k] = 2.0 * s;
+                for (int p = 0; p < c->nspec(); ++p)
+                    s += xh[(size_t)k * c->nspec() + p] * xh[(size_t)k * c->nspec() + p];
+                P[k] = c->spec_scale() * s;
             }
         }
         ADC_HIP(hipStreamSynchronize(E.stream));

@@ -609,7 +609,9 @@ void sigma_block(adc_ctx* c, const double* X, double* Yout, int nvec) {
 }
 
 void sigma_eager(adc_ctx* c, const double* X, double* Y, int nvec, int precision) {
-    if (precision == 1)
+    if (c->uhf)
+        sigma_uhf(c, X, Y, nvec);
+    else if (precision == 1)
         sigma_block<float, bf16_t>(c, X, Y, nvec);
     else if (precision == 2)
         sigma_block<float, float>(c, X, Y, nvec);
@@ -737,6 +739,11 @@ void sigma(adc_ctx* c, const double* X, double* Y, int nvec, int precision) {
 // sequence above; pp is the particle-particle (EA) / hole-hole (IP) term, whose
 // four-index rebuild is counted once per unique (ac|bd), Naux V^2 (V^2 + 1).
 void sigma_cost(const adc_ctx* c, int nvec, double* total, double* pp) {
+    if (c->uhf) {
+        sigma_cost_uhf(c, nvec, total);
+        *pp = 0.0;
+        return;
+    }
     const double n = nvec, O = c->O, V = c->V, Q = c->Q;
     double t = 0.0, p = 0.0;
     if (c->kind == ADC_EA) {

@@ -12,6 +12,10 @@ static const double SQ3 = 1.7320508075688772;
 static const double ALI = 0.5 * (1.0 + 1.0 / SQ3), BEI = 0.5 * (1.0 - 1.0 / SQ3);
 
 void spec_amplitudes(adc_ctx* c, const double* vecs, int nvec, double* Xout) {
+    if (c->uhf) {
+        spec_amplitudes_uhf(c, vecs, nvec, Xout);
+        return;
+    }
     Engine& E = c->E;
     E.ext.Z = nvec;
     const int O = c->O, V = c->V, N = c->N, n1 = c->n1, np = (int)c->n2p;

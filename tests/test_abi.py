@@ -50,6 +50,15 @@ def test_host_validation_without_gpu():
     assert lib.adc_batch_davidson(arr, 1, 1, 1 << 16, e, None, None, None, None) == adc.ADC_E_ARG
     assert lib.adc_batch_davidson(arr, 1, 1, 2 | (65 << 8), e, None, None, None, None) == adc.ADC_E_ARG
     lib.adc_destroy(None)
+    # the unrestricted setup: argument checks before any device work
+    su = lib.adc_setup_u
+    assert su(None, dummy, dummy, dummy, 2, 1, 6, 4, 2, 1, ctypes.byref(h)) == adc.ADC_E_ARG
+    assert su(dummy, dummy, dummy, dummy, 2, 1, 6, 4, 3, 1, ctypes.byref(h)) == adc.ADC_E_ARG
+    assert "order 2" in adc.last_error()
+    assert su(dummy, dummy, dummy, dummy, 6, 1, 6, 4, 2, 1, ctypes.byref(h)) == adc.ADC_E_ARG
+    assert su(dummy, dummy, dummy, dummy, 2, 0, 6, 4, 2, 1, ctypes.byref(h)) == adc.ADC_E_ARG
+    assert su(dummy, dummy, dummy, dummy, 2, 1, 6, 4, 2, 5, ctypes.byref(h)) == adc.ADC_E_ARG
+    assert su(dummy, dummy, dummy, dummy, 2, 1, 6, 4, 2, 1, None) == adc.ADC_E_ARG
     # the batch object: argument checks before any device work
     assert lib.adc_setup_batch(1, None, ctypes.byref(h)) == adc.ADC_E_ARG
     assert lib.adc_setup_batch(0, dummy, ctypes.byref(h)) == adc.ADC_E_ARG
