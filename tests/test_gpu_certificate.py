@@ -1,0 +1,89 @@
+"""Residual certificate of the GPU roots (eigenproblem of Eq. 15): the vectors
+the GPU solver returns go through a Rayleigh-Ritz step with the CPU oracle's
+sigma, whose residual norms give Kato-Temple bounds on the exact eigenvalues
+of the oracle's M (oracle/certificate.py).  The GPU energies must lie within
+1e-6 Eh of every point of the certified interval, and the interval must be
+narrower than 1e-6 Eh.  The solver is asked for one root more than is
+certified (the last Ritz pair bounds the gap above the one before it).
+
+* EA-ADC(3), O=20, V=180, Naux=600, 8 roots: FP64 and the mixed solves
+  (BF16 products, then FP64 refinement); the stored oracle roots must lie in
+  the certified intervals too.
+* EA-ADC(3), O=40, V=460, Naux=1400, 16 roots (mixed BF16 -> FP32 -> FP64):
+  only when ADC_FULL_SIZE=1 (the oracle's sigma on 17 vectors takes about ten
+  minutes on the host).
+
+The certificate assumes the solver missed no root below or between the
+computed ones; residuals cannot show that (the stored oracle solve and the
+GPU solve agree on it at the smaller size)."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "ea_adc3_o20v180_roots.json")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _solve_and_certify(key, nroots, block, precision, tol_r):
+    import paper_2012_06714_amd as adc
+    from oracle.certificate import certify
+    from oracle.radc import RADC
+    from synthetic import make_system
+    eps, B, wl = make_system(key)
+    _say(f"case certificate {wl.name}: GPU solve, {nroots} + 1 roots, precision {precision}")
+    ctx = adc.Context(torch.tensor(eps, device="cuda"), B, wl.nocc, wl.order, wl.kind)
+    for k, v in (("precision", precision), ("block", block), ("tol_e", 1e-8), ("tol_r", tol_r),
+                 ("max_iter", 300)):
+        ctx.set_option(k, v)
+    e, _, vecs, it, conv = ctx.davidson(nroots + 1, want_vectors=True)
+    X = vecs.cpu().numpy()
+    ctx.close()
+    del ctx, vecs
+    assert conv
+    _say(f"  {it} iterations; oracle Rayleigh-Ritz on the {nroots + 1} vectors")
+    ref = RADC(eps, B, wl.nocc, wl.order, wl.kind, lazy=True)
+    del B
+    theta, b = certify(lambda V: ref.sigma(V), X)
+    e = np.array(e[:nroots])
+    lo, hi = b["lower"], b["upper"]
+    dev = np.maximum(np.abs(e - lo), np.abs(e - hi))
+    _say(f"  certified widths max {np.max(hi - lo):.3e} Eh, residuals max "
+         f"{np.max(b['weinstein']):.3e} Eh, gaps min {np.min(b['gap']):.3e} Eh, "
+         f"max distance GPU root - interval {np.max(dev):.3e} Eh")
+    assert np.all(b["disjoint"])
+    assert np.max(hi - lo) <= 1e-6
+    assert np.max(dev) <= 1e-6
+    return lo, hi
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_certified_roots_o20v180(precision):
+    lo, hi = _solve_and_certify("c2", 8, 16, precision, 1e-9)
+    ref = json.load(open(GOLDEN))
+    e_ref = np.array(ref["energies_Eh"])
+    # the stored oracle roots lie in the intervals up to rounding: the
+    # Rayleigh quotients are FP64 sums over the whole space, whose rounding at
+    # |E| ~ 1e6 Eh reaches 1e-9 .. 1e-8 Eh (the intervals themselves are
+    # narrower than one unit in the last place there); slack 1e-13 |E|
+    slack = 1e-13 * np.abs(e_ref)
+    out = np.maximum(lo - e_ref, e_ref - hi)
+    _say(f"  stored oracle roots: max distance outside the intervals {np.max(out):.3e} Eh")
+    assert np.all(out <= slack)
+
+
+@pytest.mark.skipif(os.environ.get("ADC_FULL_SIZE") != "1",
+                    reason="the oracle's sigma on 17 vectors of this size takes minutes: "
+                           "set ADC_FULL_SIZE=1")
+def test_certified_roots_o40v460():
+    _solve_and_certify("c3", 16, 32, 2, 3e-9)
