@@ -402,37 +402,54 @@ k_gemm(const TI* __restrict__ A, const TI* __restrict__ B, TO* __restrict__ C, G
                     stage[(i * 16 + MT::row(lg, r)) * LDC + jj * 16 + li] =
                         alpha * acc[i][p * TNP + jj][r];
         __syncthreads();
+        // one run = 4 consecutive columns of one row; a lane keeps the same
+        // columns across its runs (64 is a multiple of the runs per row), so
+        // the column split is computed once per pass and the row split
+        // advanced incrementally (no 64-bit division per run)
+        constexpr int RPR = WNP / 4;              // runs per row
+        static_assert(64 % RPR == 0, "epilogue: runs per row must divide 64");
+        constexpr int RSTEP = 64 / RPR;           // rows between a lane's runs
+        const int c4 = (lane % RPR) * 4;
+        const long long n = n0 + wn * WN + p * WNP + c4;
+        const long long n1 = n / g.csplit, n2 = n - n1 * g.csplit;
+        const bool nrun = n + 3 < g.N && g.cs2 == 1 && n2 + 3 < g.csplit;
+        long long m = m0 + wm * WM + lane / RPR;
+        long long m1 = m / g.rsplit, m2 = m - m1 * g.rsplit;
+        const long long coff = n1 * g.cs1 + n2 * g.cs2;
 #pragma unroll 4
-        for (int q = lane; q < RUNS; q += 64) {
-            const int row = q / (WNP / 4), c4 = (q % (WNP / 4)) * 4;
-            const long long m = m0 + wm * WM + row;
-            const long long n = n0 + wn * WN + p * WNP + c4;
-            if (m >= g.M || n >= g.N) continue;
-            const acc_t* sv = stage + row * LDC + c4;
-            const long long m1 = m / g.rsplit, m2 = m - m1 * g.rsplit;
-            const long long n1 = n / g.csplit, n2 = n - n1 * g.csplit;
-            TO* dst = C + m1 * g.rs1 + m2 * g.rs2 + n1 * g.cs1 + n2 * g.cs2;
-            const bool run = n + 3 < g.N && g.cs2 == 1 && n2 + 3 < g.csplit &&
-                             (reinterpret_cast<uintptr_t>(dst) % (4 * sizeof(TO))) == 0;
-            if (run) {
-                to4 o;
-                if (beta != acc_t(0)) {
-                    const to4 old = *reinterpret_cast<const to4*>(dst);
+        for (int row = lane / RPR; row < WM; row += RSTEP) {
+            if (m < g.M && n < g.N) {
+                const acc_t* sv = stage + row * LDC + c4;
+                TO* dst = C + m1 * g.rs1 + m2 * g.rs2 + coff;
+                const bool run =
+                    nrun && (reinterpret_cast<uintptr_t>(dst) % (4 * sizeof(TO))) == 0;
+                if (run) {
+                    to4 o;
+                    if (beta != acc_t(0)) {
+                        const to4 old = *reinterpret_cast<const to4*>(dst);
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) o[e] = to_out<TO, acc_t>(sv[e] + beta * (acc_t)old[e]);
+                        for (int e = 0; e < 4; ++e)
+                            o[e] = to_out<TO, acc_t>(sv[e] + beta * (acc_t)old[e]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) o[e] = to_out<TO, acc_t>(sv[e]);
+                    }
+                    *reinterpret_cast<to4*>(dst) = o;
                 } else {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) o[e] = to_out<TO, acc_t>(sv[e]);
+                    for (int e = 0; e < 4 && n + e < g.N; ++e) {
+                        const long long ne = n + e, ne1 = ne / g.csplit, ne2 = ne - ne1 * g.csplit;
+                        TO* de = C + m1 * g.rs1 + m2 * g.rs2 + ne1 * g.cs1 + ne2 * g.cs2;
+                        acc_t v = sv[e];
+                        if (beta != acc_t(0)) v += beta * (acc_t)(*de);
+                        *de = to_out<TO, acc_t>(v);
+                    }
                 }
-                *reinterpret_cast<to4*>(dst) = o;
-            } else {
-                for (int e = 0; e < 4 && n + e < g.N; ++e) {
-                    const long long ne = n + e, ne1 = ne / g.csplit, ne2 = ne - ne1 * g.csplit;
-                    TO* de = C + m1 * g.rs1 + m2 * g.rs2 + ne1 * g.cs1 + ne2 * g.cs2;
-                    acc_t v = sv[e];
-                    if (beta != acc_t(0)) v += beta * (acc_t)(*de);
-                    *de = to_out<TO, acc_t>(v);
-                }
+            }
+            m += RSTEP;
+            m2 += RSTEP;
+            while (m2 >= g.rsplit) {
+                m2 -= g.rsplit;
+                ++m1;
             }
         }
     }

@@ -314,6 +314,40 @@ __global__ void k_arrange(ArrSpec a, long long x0, long long total, TB* __restri
     }
 }
 
+// The same arrangement when one term reads its second index (y) with unit
+// stride and its last index (w) with a large one: a 32x32 (y, w) tile of that
+// term is read along y (coalesced), transposed through LDS and written along
+// w; the other term (if any) has unit stride in w and is read directly.
+// Tiles: grid.x over (y, w) tiles, grid.y over z, grid.z over the block's
+// leading indices.
+struct ArrTerm {
+    long long s[4];
+    double al;
+};
+template <typename TB>
+__global__ void k_arrange_tiled(const double* __restrict__ src, ArrTerm tr, ArrTerm dr,
+                                bool direct, long long e1, long long e2, long long e3,
+                                long long x0, int ntw, TB* __restrict__ out) {
+    __shared__ double tile[32][33];
+    const int ty = threadIdx.y, tx = threadIdx.x;   // 8 x 32
+    const long long y0 = (long long)(blockIdx.x / ntw) * 32, w0 = (long long)(blockIdx.x % ntw) * 32;
+    const long long z = blockIdx.y, xl = blockIdx.z, x = x0 + xl;
+    const double* base = src + x * tr.s[0] + z * tr.s[2];
+    for (int r = ty; r < 32; r += 8) {
+        const long long w = w0 + r, y = y0 + tx;
+        tile[r][tx] = (w < e3 && y < e1) ? base[y * tr.s[1] + w * tr.s[3]] : 0.0;
+    }
+    __syncthreads();
+    const double* dbase = src + x * dr.s[0] + z * dr.s[2];
+    for (int r = ty; r < 32; r += 8) {
+        const long long y = y0 + r, w = w0 + tx;
+        if (y >= e1 || w >= e3) continue;
+        double v = tr.al * tile[tx][r];
+        if (direct) v += dr.al * dbase[y * dr.s[1] + w * dr.s[3]];
+        out[((xl * e1 + y) * e2 + z) * e3 + w] = narrow_to<TB>(v);
+    }
+}
+
 static ArrSpec arr(const double* src, long long e1, long long e2, long long e3,
                    std::array<long long, 4> s, double al = 1.0,
                    std::array<long long, 4> r = {0, 0, 0, 0}, double be = 0.0) {
@@ -350,8 +384,28 @@ static void blocked_nt(adc_ctx* c, bool arranged_a, long long M_or_N, const ArrS
         const long long total = n * rows * K;
         long long g = (total + 255) / 256;
         g = std::max<long long>(1, std::min<long long>(g, 1LL << 20));
-        hipLaunchKernelGGL(k_arrange<TB>, dim3((unsigned)g), dim3(256), 0, E.stream, a, x0, total,
-                           sl);
+        // a term with unit stride in y and not in w goes through the LDS
+        // transpose (the other term, if any, must have unit stride in w)
+        const bool t_s = a.s[1] == 1 && a.s[3] != 1 && (a.be == 0.0 || a.r[3] == 1);
+        const bool t_r = !t_s && a.be != 0.0 && a.r[1] == 1 && a.r[3] != 1 && a.s[3] == 1;
+        if ((t_s || t_r) && a.e2 <= 65535 && n <= 65535) {
+            ArrTerm tr, dr;
+            for (int k = 0; k < 4; ++k) {
+                tr.s[k] = t_s ? a.s[k] : a.r[k];
+                dr.s[k] = t_s ? a.r[k] : a.s[k];
+            }
+            tr.al = t_s ? a.al : a.be;
+            dr.al = t_s ? a.be : a.al;
+            const long long nty = (rows + 31) / 32, ntw = (a.e3 + 31) / 32;
+            ADC_REQUIRE(nty * ntw < (1LL << 31), "arrange: too many tiles");
+            hipLaunchKernelGGL(k_arrange_tiled<TB>, dim3((unsigned)(nty * ntw), (unsigned)a.e2,
+                                                         (unsigned)n),
+                               dim3(32, 8), 0, E.stream, a.src, tr, dr, a.be != 0.0, rows, a.e2,
+                               a.e3, x0, (int)ntw, sl);
+        } else {
+            hipLaunchKernelGGL(k_arrange<TB>, dim3((unsigned)g), dim3(256), 0, E.stream, a, x0,
+                               total, sl);
+        }
         ADC_HIP(hipGetLastError());
         if (arranged_a)
             gemm_map<TB, TO>(E, false, true, n * rows, M_or_N, K, alpha, sl, K, other, ld_other,
