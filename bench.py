@@ -37,13 +37,15 @@ sys.path.insert(0, ROOT)
 PEAKS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 # HBM bytes per particle-particle launch (one sigma call) from two rocprofv3
 # counter runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, the factors of a plain
-# 1 GiB copy), summarised in profiles/pp_term_ea_adc3_o20v180_hbm_bytes.md.
-# Valid for the kernels as measured; re-measure whenever they change.
+# 1 GiB copy), summarised in profiles/pp_term_ea_adc3_o20v180_hbm_bytes.md and
+# profiles/pp_term_ea_adc3_o60v968_hbm_bytes.md.  Valid for the kernels as
+# measured; re-measure whenever they change (the O=20, V=180 figures predate
+# the current GEMM epilogue and are not reported for it).
 # sigma levels: FP64; BF16 products (FP32 storage) with FP64 refinement in
 # the solver; FP32 products, used by the solver as a middle phase (BF16 ->
 # FP32 -> FP64)
 LEVEL = {"fp64": 0, "mixed": 1, "mixed3": 2}
-PP_TRAFFIC = {("ea-adc3-o20v180", "fp64"): 5.1352e+10, ("ea-adc3-o20v180", "mixed"): 5.8496e+09}
+PP_TRAFFIC = {("ea-adc3-o60v968", "mixed"): 8.5325e+12}
 HBM_GBPS = 8000.0
 
 
