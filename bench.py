@@ -24,6 +24,8 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --workload c5 [--systems 64] [--max-nocc N]
          (the batched EA-ADC(2) family: lockstep solves with one graph launch
           per iteration against one-by-one solves)
+       python bench.py --workload c5 --learned [--train 40] [--systems 64]
+         (learned vs diagonal preconditioner on held-out systems of that family)
 """
 import argparse
 import json
@@ -171,6 +173,104 @@ def bench_batch(args):
     return 0
 
 
+def bench_learned(args):
+    """The learned preconditioner on the batched EA-ADC(2) family: pairs from
+    the solves of `train` training systems (seeds 100..), the network fitted
+    by the library's kernels, then the held-out systems 0..systems-1 solved
+    with the diagonal and with the learned correction (same tolerances).
+    Reports iterations and time to 1e-6 Eh of each system's converged roots."""
+    import numpy as np
+    import torch
+    import paper_2012_06714_amd as adc
+    from paper_2012_06714_amd import mlp_train
+    from synthetic import make_batch_system
+    dev = torch.device("cuda:0")
+    nroots, block = 4, 8
+
+    def ctx_for(s):
+        eps, B, (O, V, Q) = make_batch_system(s, args.max_nocc)
+        c = adc.Context(torch.tensor(eps, device=dev), B, O, 2, "ea")
+        for k, v in (("tol_e", 1e-8), ("tol_r", 1e-5), ("block", block), ("max_space", 64),
+                     ("max_iter", 400)):
+            c.set_option(k, v)
+        return c, (O, V, Q)
+
+    Fs, As, Ts = [], [], []
+    t0 = time.perf_counter()
+    for k in range(args.train):
+        s = 100 + k
+        c, dims = ctx_for(s)
+        F, a, t, it = mlp_train.collect_pairs(c, nroots, 1024, s, torch, max_records=60, block=block)
+        Fs.append(F)
+        As.append(a)
+        Ts.append(t)
+        c.close()
+        log(f"bench: training system {s} {dims}: {it} iterations, {F.shape[0]} pairs")
+    F, a, t = torch.cat(Fs), torch.cat(As), torch.cat(Ts)
+    t_collect = time.perf_counter() - t0
+    c, _ = ctx_for(0)
+    t0 = time.perf_counter()
+    params, hist = mlp_train.train(c, F, a, t, args.train_steps, 1e-3, 8192, 3, torch, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    c.close()
+    rows = []
+    for s in range(args.systems):
+        c, dims = ctx_for(s)
+        res = {}
+        for mode in ("diagonal", "learned"):
+            if mode == "learned":
+                c.precond_mlp(params)
+                c.set_option("precond", 1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e, P, _, it, ok = c.davidson(nroots, want_vectors=False)
+            dt = time.perf_counter() - t0
+            ts, th, rn, mx = c.history(nroots)
+            res[mode] = {"iterations": it, "seconds": dt, "converged": bool(ok), "energies": e,
+                         "ts": ts, "th": th}
+        e_ref = np.array(res["diagonal"]["energies"])
+        for mode in ("diagonal", "learned"):
+            r = res[mode]
+            err = np.max(np.abs(r["th"] - e_ref[None, :]), axis=1)
+            hit = np.nonzero(err <= 1e-6)[0]
+            r["t_1e6"] = float(r["ts"][hit[0]]) if hit.size else None
+        fb = c.mlp_status()[1]
+        c.close()
+        d, l = res["diagonal"], res["learned"]
+        rows.append({"system": s, "dims": dims, "diag_it": d["iterations"], "learned_it": l["iterations"],
+                     "diag_t_1e6": d["t_1e6"], "learned_t_1e6": l["t_1e6"], "fallbacks": fb,
+                     "max_dE": float(np.max(np.abs(np.array(l["energies"]) - e_ref))),
+                     "both_converged": d["converged"] and l["converged"]})
+        log(f"bench: system {s} {dims}: diagonal {d['iterations']} it, learned {l['iterations']} it "
+            f"(fallbacks {fb}), max |dE| {rows[-1]['max_dE']:.1e}")
+    di = np.array([r["diag_it"] for r in rows], dtype=float)
+    li = np.array([r["learned_it"] for r in rows], dtype=float)
+    dt = np.array([r["diag_t_1e6"] or np.nan for r in rows])
+    lt = np.array([r["learned_t_1e6"] or np.nan for r in rows])
+    out = {
+        "metric": "EA-ADC(2) Davidson iterations, learned vs diagonal preconditioner",
+        "value": float(np.mean(li)), "unit": "iterations (mean)", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": float(np.nansum(lt)) * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batched ea-adc2, held-out systems 0..{args.systems - 1}, "
+                               f"trained on systems 100..{99 + args.train}",
+                   "nroots": nroots, "block": block, "train_pairs": int(F.shape[0]),
+                   "train_steps": args.train_steps, "max_nocc": args.max_nocc},
+        "diagonal": {"iterations_mean": float(np.mean(di)), "time_to_1e-6_Eh_s_sum": float(np.nansum(dt))},
+        "learned": {"iterations_mean": float(np.mean(li)), "time_to_1e-6_Eh_s_sum": float(np.nansum(lt)),
+                    "systems_with_fallback": int(sum(1 for r in rows if r["fallbacks"])),
+                    "max_abs_energy_difference_Eh": float(max(r["max_dE"] for r in rows)),
+                    "all_converged": all(r["both_converged"] for r in rows)},
+        "training": {"collect_s": t_collect, "train_s": t_train, "loss_first": float(hist[0]),
+                     "loss_last": float(np.mean(hist[-50:]))},
+        "per_system": [{k: v for k, v in r.items()} for r in rows],
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 GOLDEN_C2 = os.path.join(ROOT, "tests", "golden", "ea_adc3_o20v180_roots.json")
 
 
@@ -240,6 +340,11 @@ def main():
                     help="batched workload: systems resident and solved together")
     ap.add_argument("--max-nocc", type=int, default=None,
                     help="batched workload: cap on the occupied count (smaller stand-ins)")
+    ap.add_argument("--learned", action="store_true",
+                    help="batched workload: learned vs diagonal preconditioner on held-out systems")
+    ap.add_argument("--train", type=int, default=40,
+                    help="learned preconditioner: training systems (seeds 100, 101, ...)")
+    ap.add_argument("--train-steps", type=int, default=1500, help="learned preconditioner: Adam steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -248,7 +353,7 @@ def main():
         return 2
 
     if args.workload in ("c5", "batch"):
-        return bench_batch(args)
+        return bench_learned(args) if args.learned else bench_batch(args)
 
     import numpy as np
     import torch

@@ -223,6 +223,33 @@ static long long splitk_chunks(long long M, long long N, long long K, long long 
     return std::max<long long>(S, 1);
 }
 
+// BF16 particle-particle contractions (kind 2): a few hundred 256x256
+// workgroups over a summed index of V^2, one workgroup per CU, lose up to half
+// the chip in their last round.  Split K when that raises the filled share of
+// the rounds (the first s-1 chunks are one launch, the last another) by more
+// than 5 points (each chunk at least 4096 long, the partial results at most
+// 1 GiB, at most 8 chunks).
+static long long splitk_rounds(long long M, long long N, long long K, long long batch, size_t acc) {
+    const long long n = ((M + 255) / 256) * ((N + 255) / 256) * batch;
+    // chunks 0 .. s-2 run as one launch and the last chunk as another
+    auto rounds = [](long long w) { return (w + 255) / 256; };
+    auto filled = [&](long long s) {
+        const long long r = s == 1 ? rounds(n) : rounds(n * (s - 1)) + rounds(n);
+        return (double)(n * s) / (256.0 * (double)r);
+    };
+    long long best = 1;
+    double fb = filled(1);
+    for (long long s = 2; s <= 8; ++s) {
+        if (K / s < 4096 || s * batch > 65535) break;
+        if ((size_t)s * (size_t)(M * N * batch) * acc > (size_t(1) << 30)) break;
+        if (filled(s) > fb + 0.05) {
+            best = s;
+            fb = filled(s);
+        }
+    }
+    return best;
+}
+
 // C (accumulator type) = alpha op(A) op(B) + beta C, row-major output with
 // leading dimension ldc, through split-K when the grid would be small
 template <typename TI, typename T>
@@ -231,7 +258,8 @@ static void gemm_any(Engine& E, bool ta, bool tb, long long M, long long N, long
                      const TI* B, long long ldb, long long sB, typename AccOf<T>::type beta,
                      typename AccOf<T>::type* C, GemmOut out, long long batch, int kind) {
     using Acc = typename AccOf<T>::type;
-    long long S = splitk_chunks(M, N, K, batch, sizeof(Acc));
+    long long S = (sizeof(T) == 2 && kind == 2) ? splitk_rounds(M, N, K, batch, sizeof(Acc))
+                                                : splitk_chunks(M, N, K, batch, sizeof(Acc));
     long long Kc = K;
     if (S >= 2) {
         Kc = (K + S - 1) / S;
