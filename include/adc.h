@@ -201,7 +201,7 @@ int adc_set_setup_option(const char* key, double value);
  *                 it stages the rows it needs, one block at a time; 0 = back
  *                 on the device (default).  Needs ea_layout -1, 1 or 2
  *   "gemm_config" -1 = tile configuration of each matrix-core product chosen
- *                 by the autotuner or heuristic (default); 0..7 = that
+ *                 by the autotuner or heuristic (default); 0..8 = that
  *                 configuration forced on every product of this context (ids
  *                 from adc_gemm_configs; one not compiled for a product's
  *                 type runs as 0)

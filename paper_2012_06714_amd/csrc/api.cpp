@@ -269,8 +269,8 @@ int adc_set_option(adc_ctx* c, const char* key, double value) {
         });
     } else if (k == "gemm_config") {
         // force one matrix-core tile configuration on every product (-1: automatic)
-        if (value < -1 || value > 7 || value != std::floor(value))
-            return fail(c, ADC_E_ARG, "gemm_config: -1 or a configuration id 0..7");
+        if (value < -1 || value > 8 || value != std::floor(value))
+            return fail(c, ADC_E_ARG, "gemm_config: -1 or a configuration id 0..8");
         c->E.force_cfg = (int)value;
         adc::drop_graphs(c);
     } else if (k == "pp_slab_mb") {
@@ -472,7 +472,7 @@ int adc_gemm(int dtype, int ta, int tb, long long M, long long N, long long K, d
     if (!A || !B || !C) return fail(nullptr, ADC_E_ARG, "adc_gemm: NULL operand");
     if (lda < (ta ? M : K) || ldb < (tb ? K : N) || (!map && ldc < N))
         return fail(nullptr, ADC_E_ARG, "adc_gemm: leading dimension too small");
-    if (config < -1 || config > 7) return fail(nullptr, ADC_E_ARG, "adc_gemm: config -1..7");
+    if (config < -1 || config > 8) return fail(nullptr, ADC_E_ARG, "adc_gemm: config -1..8");
     adc::GemmOut out = adc::GemmOut::rowmajor(ldc);
     if (map) {
         if (map[0] < 0 || map[3] < 0)

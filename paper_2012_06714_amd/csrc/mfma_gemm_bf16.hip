@@ -16,9 +16,9 @@ ADC_INST(float, bf16_t, bf16_t)
 
 template <>
 int gemm_candidates<bf16_t>(int* ids) {
-    static const int c[] = {0, 1, 6, 7};
-    for (int k = 0; k < 4; ++k) ids[k] = c[k];
-    return 4;
+    static const int c[] = {0, 1, 6, 7, 8};
+    for (int k = 0; k < 5; ++k) ids[k] = c[k];
+    return 5;
 }
 
 }  // namespace adc

@@ -113,6 +113,131 @@ struct Chunk {
     }
 };
 
+// Origin (m0, n0) of this workgroup's BM x BN output tile.  Workgroups are
+// dealt round-robin to the 8 XCDs, so the linear id is regrouped to give each
+// XCD a contiguous run of tiles, walked in column groups of 8 row tiles
+// (operand reuse in that XCD's L2).
+template <int BM, int BN>
+__device__ __forceinline__ void tile_origin(const GemmShape& g, long long& m0, long long& n0) {
+    const long long ntn = (g.N + BN - 1) / BN, ntm = (g.M + BM - 1) / BM;
+    // hardware id h goes to XCD h mod 8; XCD x takes the logical ids
+    // [x*q + min(x, r), ...) of length q + (x < r), q = nwg / 8, r = nwg mod 8
+    long long pid = blockIdx.x;
+    const long long nwg = (long long)gridDim.x;
+    {
+        const long long x = pid & 7, k = pid >> 3, q = nwg >> 3, r = nwg & 7;
+        pid = x * q + (x < r ? x : r) + k;
+    }
+    const long long GROUP = 8;
+    const long long per_group = GROUP * ntn;
+    const long long grp = pid / per_group;
+    const long long first_m = grp * GROUP;
+    const long long gsz = std::min(ntm - first_m, GROUP);
+    const long long tmi = first_m + (pid % per_group) % gsz;
+    const long long tni = (pid % per_group) / gsz;
+    m0 = tmi * BM;
+    n0 = tni * BN;
+}
+
+// Element offsets of this workgroup's batch entry (grid z, two levels) in the
+// operands and the result.
+struct BatchOff {
+    long long a, b, c;
+};
+__device__ __forceinline__ BatchOff batch_offsets(const GemmShape& g) {
+    const long long bz = g.z0 + blockIdx.z;
+    const long long b1 = bz / g.n2, b2 = bz - b1 * g.n2;
+    return {b1 * g.sA + b2 * g.sA2, b1 * g.sB + b2 * g.sB2, b1 * g.sC + b2 * g.sC2};
+}
+
+// Store of one wave's WM x WN block of accumulators, whose first output row
+// and column are (mw, nw).  The block is staged in LDS at `stage` (alpha
+// applied), in NPASS passes over column slices, and stored back through the
+// output index map in runs of 4 consecutive columns: one vector store per run
+// when the run is contiguous and aligned in the map, element stores otherwise.
+// Every wave of the workgroup calls it (it synchronises the workgroup).
+template <typename T, typename TO, int WM, int WN, int NPASS>
+__device__ __forceinline__ void store_tile(typename Mfma<T>::accv (&acc)[WM / 16][WN / 16],
+                                           typename Mfma<T>::acc_t* stage, TO* __restrict__ C,
+                                           const GemmShape& g, long long mw, long long nw,
+                                           int lane, typename Mfma<T>::acc_t alpha,
+                                           typename Mfma<T>::acc_t beta) {
+    using MT = Mfma<T>;
+    using acc_t = typename MT::acc_t;
+    constexpr int TM = WM / 16, TN = WN / 16;
+    constexpr int PAD = 16 / (int)sizeof(acc_t);
+    constexpr int WNP = WN / NPASS;          // columns per pass
+    constexpr int TNP = TN / NPASS;          // 16-column blocks per pass
+    constexpr int LDC = WNP + PAD;           // staged row (elements)
+    constexpr int RUNS = WM * WNP / 4;       // runs of 4 per wave and pass
+    static_assert(TN % NPASS == 0 && RUNS % 64 == 0, "epilogue tiling");
+    typedef TO to4 __attribute__((ext_vector_type(4)));
+    const int li = lane & 15, lg = lane >> 4;
+#pragma unroll
+    for (int p = 0; p < NPASS; ++p) {
+        __syncthreads();    // operand tiles (or the previous pass) no longer read
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int jj = 0; jj < TNP; ++jj)
+                    stage[(i * 16 + MT::row(lg, r)) * LDC + jj * 16 + li] =
+                        alpha * acc[i][p * TNP + jj][r];
+        __syncthreads();
+        // one run = 4 consecutive columns of one row; a lane keeps the same
+        // columns across its runs (64 is a multiple of the runs per row), so
+        // the column split is computed once per pass and the row split
+        // advanced incrementally (no 64-bit division per run)
+        constexpr int RPR = WNP / 4;              // runs per row
+        static_assert(64 % RPR == 0, "epilogue: runs per row must divide 64");
+        constexpr int RSTEP = 64 / RPR;           // rows between a lane's runs
+        const int c4 = (lane % RPR) * 4;
+        const long long n = nw + p * WNP + c4;
+        const long long n1 = n / g.csplit, n2 = n - n1 * g.csplit;
+        const bool nrun = n + 3 < g.N && g.cs2 == 1 && n2 + 3 < g.csplit;
+        long long m = mw + lane / RPR;
+        long long m1 = m / g.rsplit, m2 = m - m1 * g.rsplit;
+        const long long coff = n1 * g.cs1 + n2 * g.cs2;
+#pragma unroll 4
+        for (int row = lane / RPR; row < WM; row += RSTEP) {
+            if (m < g.M && n < g.N) {
+                const acc_t* sv = stage + row * LDC + c4;
+                TO* dst = C + m1 * g.rs1 + m2 * g.rs2 + coff;
+                const bool run =
+                    nrun && (reinterpret_cast<uintptr_t>(dst) % (4 * sizeof(TO))) == 0;
+                if (run) {
+                    to4 o;
+                    if (beta != acc_t(0)) {
+                        const to4 old = *reinterpret_cast<const to4*>(dst);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            o[e] = to_out<TO, acc_t>(sv[e] + beta * (acc_t)old[e]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) o[e] = to_out<TO, acc_t>(sv[e]);
+                    }
+                    *reinterpret_cast<to4*>(dst) = o;
+                } else {
+                    for (int e = 0; e < 4 && n + e < g.N; ++e) {
+                        const long long ne = n + e, ne1 = ne / g.csplit, ne2 = ne - ne1 * g.csplit;
+                        TO* de = C + m1 * g.rs1 + m2 * g.rs2 + ne1 * g.cs1 + ne2 * g.cs2;
+                        acc_t v = sv[e];
+                        if (beta != acc_t(0)) v += beta * (acc_t)(*de);
+                        *de = to_out<TO, acc_t>(v);
+                    }
+                }
+            }
+            m += RSTEP;
+            m2 += RSTEP;
+            while (m2 >= g.rsplit) {
+                m2 -= g.rsplit;
+                ++m1;
+            }
+        }
+    }
+}
+
 // One workgroup of 256 threads (4 waves) computes a BM x BN tile; each wave a
 // WM x WN sub-tile of 16x16 instruction blocks.
 // A workgroup of WGM x WGN waves computes a BM x BN tile, each wave a
@@ -147,33 +272,13 @@ k_gemm(const TI* __restrict__ A, const TI* __restrict__ B, TO* __restrict__ C, G
     const int wm = wave / WAVES_N, wn = wave % WAVES_N;
     const int li = lane & 15, lg = lane >> 4;
 
-    // tile coordinates: workgroups are dealt round-robin to the 8 XCDs, so
-    // regroup the linear id so that each XCD gets a contiguous run of tiles,
-    // then walk that run in column groups of 8 row tiles (operand reuse in L2)
-    const long long ntm = (g.M + BM - 1) / BM, ntn = (g.N + BN - 1) / BN;
-    // hardware id h goes to XCD h mod 8; XCD x takes the logical ids
-    // [x*q + min(x, r), ...) of length q + (x < r), q = nwg / 8, r = nwg mod 8
-    long long pid = blockIdx.x;
-    const long long nwg = (long long)gridDim.x;
+    long long m0, n0;
+    tile_origin<BM, BN>(g, m0, n0);
     {
-        const long long x = pid & 7, k = pid >> 3, q = nwg >> 3, r = nwg & 7;
-        pid = x * q + (x < r ? x : r) + k;
-    }
-    const long long GROUP = 8;
-    const long long per_group = GROUP * ntn;
-    const long long grp = pid / per_group;
-    const long long first_m = grp * GROUP;
-    const long long gsz = std::min(ntm - first_m, GROUP);
-    const long long tmi = first_m + (pid % per_group) % gsz;
-    const long long tni = (pid % per_group) / gsz;
-    const long long m0 = tmi * BM, n0 = tni * BN;
-
-    {
-        const long long bz = g.z0 + blockIdx.z;
-        const long long b1 = bz / g.n2, b2 = bz - b1 * g.n2;
-        A += b1 * g.sA + b2 * g.sA2;
-        B += b1 * g.sB + b2 * g.sB2;
-        C += b1 * g.sC + b2 * g.sC2;
+        const BatchOff o = batch_offsets(g);
+        A += o.a;
+        B += o.b;
+        C += o.c;
     }
 
     // ---- global -> register staging ------------------------------------
@@ -371,88 +476,181 @@ k_gemm(const TI* __restrict__ A, const TI* __restrict__ B, TO* __restrict__ C, G
         compute(kt & 1);
     }
 
-    // ---- epilogue -------------------------------------------------------
-    // Each wave stages its sub-tile (alpha applied) in LDS, in passes over
-    // column slices when the whole tile does not fit, and stores it back in
-    // runs of 4 consecutive columns: one vector store per run when the run is
-    // contiguous and aligned in the output map, element stores otherwise.
+    // ---- epilogue: staged through the operand tiles' LDS ----------------
     constexpr int NW = WGM * WGN;
     constexpr int SMEM_BYTES = 2 * (BM + BN) * LDK * (int)sizeof(T);
     constexpr int PAD = 16 / (int)sizeof(acc_t);
     constexpr int NPASS = (NW * WM * (WN + PAD) * (int)sizeof(acc_t) <= SMEM_BYTES)         ? 1
                           : (NW * WM * (WN / 2 + PAD) * (int)sizeof(acc_t) <= SMEM_BYTES) ? 2
                                                                                             : 4;
-    constexpr int WNP = WN / NPASS;          // columns per pass
-    constexpr int TNP = TN / NPASS;          // 16-column blocks per pass
-    constexpr int LDC = WNP + PAD;           // staged row (elements)
-    constexpr int RUNS = WM * WNP / 4;       // runs of 4 per wave and pass
-    static_assert(TN % NPASS == 0 && RUNS % 64 == 0, "epilogue tiling");
-    static_assert(NW * WM * LDC * (int)sizeof(acc_t) <= SMEM_BYTES, "epilogue staging");
-    typedef TO to4 __attribute__((ext_vector_type(4)));
-    acc_t* stage = reinterpret_cast<acc_t*>(smem) + wave * (WM * LDC);
+    static_assert(NW * WM * (WN / NPASS + PAD) * (int)sizeof(acc_t) <= SMEM_BYTES,
+                  "epilogue staging");
+    acc_t* stage = reinterpret_cast<acc_t*>(smem) + wave * (WM * (WN / NPASS + PAD));
+    store_tile<T, TO, WM, WN, NPASS>(acc, stage, C, g, m0 + wm * WM, n0 + wn * WN, lane, alpha,
+                                     beta);
+}
+
+// BF16 NT product (A [M][K], B [N][K], both k-fastest) on a 256x256 tile of
+// 8 waves (4 x 2, a 64x128 block each) whose operand tiles go from global
+// memory straight into LDS with 16-byte LDS-DMA loads (global_load_lds): no
+// staging registers and no LDS store instructions, so the loads of the next
+// k-tile are issued before the products of the current one and have a whole
+// k-step to arrive.  Each operand and stage has an LDS array of its own: the
+// compiler then knows that the outstanding loads write the other stage, and
+// the fragment reads of this one need not wait for them.
+//
+// LDS layout of an operand tile: row r (0..255) of 64 k-values in 128 bytes,
+// its 16-byte chunk c (k = 8c .. 8c+7) at position c ^ (r mod 8).  One DMA
+// instruction of a wave fills 1 KB (8 rows) with lane l writing position
+// l mod 8 of row l / 8, so each lane loads the chunk that the XOR puts there.
+// The fragment reads of 8 consecutive rows at one chunk hit 8 distinct 16-byte
+// bank groups.  Full k-tiles need every row in bounds: rows past the operand's
+// extent are clamped to its last row (they only feed discarded outputs); the
+// ragged last k-tile is loaded through registers with zero fill.
+template <typename TO, int KIND>
+__global__ void __launch_bounds__(512)
+k_gemm_lds(const bf16_t* __restrict__ A, const bf16_t* __restrict__ B, TO* __restrict__ C,
+           GemmShape g, float alpha, float beta) {
+    using MT = Mfma<bf16_t>;
+    using accv = typename MT::accv;
+    constexpr int BM = 256, BN = 256, BK = 64, WGN = 2, NW = 8;
+    constexpr int WM = 64, WN = 128, TM = WM / 16, TN = WN / 16;
+    constexpr int ROWB = BK * 2;                      // bytes per LDS row
+    constexpr int NPASS = 2, LDC = WN / NPASS + 4;    // epilogue: FP32 rows of 68
+    constexpr int STAGE = WM * LDC * 4;               // epilogue bytes per wave
+    constexpr int BUF = (BM * ROWB > 2 * STAGE) ? BM * ROWB : 2 * STAGE;
+    constexpr int NBLK = BM * ROWB / 1024 / NW;       // 1 KB DMA blocks per wave and tile
+    static_assert(BM == BN && BM * ROWB == 32768 && NBLK * NW * 1024 == 32768,
+                  "operand tile layout");
+    __shared__ __attribute__((aligned(1024))) char la0[BUF], la1[BUF], lb0[BUF], lb1[BUF];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / WGN, wn = wave % WGN;
+    const int li = lane & 15, lg = lane >> 4;
+
+    long long m0, n0;
+    tile_origin<BM, BN>(g, m0, n0);
+    {
+        const BatchOff o = batch_offsets(g);
+        A += o.a;
+        B += o.b;
+        C += o.c;
+    }
+
+    // this lane's NBLK rows of each operand tile (1 KB blocks wave, wave + NW,
+    // ...) and the k-chunk it loads into each
+    const int rl = lane >> 3;
+    const int kc = (lane & 7) ^ rl;
+    const bf16_t* pa[NBLK];
+    const bf16_t* pb[NBLK];
 #pragma unroll
-    for (int p = 0; p < NPASS; ++p) {
-        __syncthreads();    // operand tiles (or the previous pass) no longer read
+    for (int j = 0; j < NBLK; ++j) {
+        const int r = 8 * (wave + NW * j) + rl;
+        const long long ra = m0 + r < g.M ? m0 + r : g.M - 1;
+        const long long rb = n0 + r < g.N ? n0 + r : g.N - 1;
+        pa[j] = A + ra * g.lda + kc * 8;
+        pb[j] = B + rb * g.ldb + kc * 8;
+    }
+    typedef __attribute__((address_space(1))) void gvoid;
+    typedef __attribute__((address_space(3))) void lvoid;
+    // a full k-tile (k0 + BK <= K) by DMA
+    auto dma = [&](char* sa, char* sb, long long k0) {
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+        for (int j = 0; j < NBLK; ++j) {
+            __builtin_amdgcn_global_load_lds((gvoid*)(pa[j] + k0),
+                                             (lvoid*)(sa + (wave + NW * j) * 1024), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((gvoid*)(pb[j] + k0),
+                                             (lvoid*)(sb + (wave + NW * j) * 1024), 16, 0, 0);
+        }
+    };
+    // the ragged last k-tile through registers: chunks inside K are one
+    // 16-byte load, chunks past K (or of rows past the operand) are zero, and
+    // a chunk that K cuts (K not a multiple of 8) is read element by element
+    auto tail = [&](char* sa, char* sb, long long k0) {
+        const long long k = k0 + kc * 8;
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+        for (int j = 0; j < NBLK; ++j) {
+            const int r = 8 * (wave + NW * j) + rl;
 #pragma unroll
-                for (int jj = 0; jj < TNP; ++jj)
-                    stage[(i * 16 + MT::row(lg, r)) * LDC + jj * 16 + li] =
-                        alpha * acc[i][p * TNP + jj][r];
-        __syncthreads();
-        // one run = 4 consecutive columns of one row; a lane keeps the same
-        // columns across its runs (64 is a multiple of the runs per row), so
-        // the column split is computed once per pass and the row split
-        // advanced incrementally (no 64-bit division per run)
-        constexpr int RPR = WNP / 4;              // runs per row
-        static_assert(64 % RPR == 0, "epilogue: runs per row must divide 64");
-        constexpr int RSTEP = 64 / RPR;           // rows between a lane's runs
-        const int c4 = (lane % RPR) * 4;
-        const long long n = n0 + wn * WN + p * WNP + c4;
-        const long long n1 = n / g.csplit, n2 = n - n1 * g.csplit;
-        const bool nrun = n + 3 < g.N && g.cs2 == 1 && n2 + 3 < g.csplit;
-        long long m = m0 + wm * WM + lane / RPR;
-        long long m1 = m / g.rsplit, m2 = m - m1 * g.rsplit;
-        const long long coff = n1 * g.cs1 + n2 * g.cs2;
-#pragma unroll 4
-        for (int row = lane / RPR; row < WM; row += RSTEP) {
-            if (m < g.M && n < g.N) {
-                const acc_t* sv = stage + row * LDC + c4;
-                TO* dst = C + m1 * g.rs1 + m2 * g.rs2 + coff;
-                const bool run =
-                    nrun && (reinterpret_cast<uintptr_t>(dst) % (4 * sizeof(TO))) == 0;
-                if (run) {
-                    to4 o;
-                    if (beta != acc_t(0)) {
-                        const to4 old = *reinterpret_cast<const to4*>(dst);
+            for (int o = 0; o < 2; ++o) {
+                const bf16_t* p = (o == 0 ? pa[j] : pb[j]) + k0;
+                const bool row_ok = o == 0 ? m0 + r < g.M : n0 + r < g.N;
+                uint4 v = {0u, 0u, 0u, 0u};
+                if (row_ok && k + 8 <= g.K) {
+                    v = *reinterpret_cast<const uint4*>(p);
+                } else if (row_ok && k < g.K) {
+                    bf16_t e8[8];
 #pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            o[e] = to_out<TO, acc_t>(sv[e] + beta * (acc_t)old[e]);
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) o[e] = to_out<TO, acc_t>(sv[e]);
-                    }
-                    *reinterpret_cast<to4*>(dst) = o;
-                } else {
-                    for (int e = 0; e < 4 && n + e < g.N; ++e) {
-                        const long long ne = n + e, ne1 = ne / g.csplit, ne2 = ne - ne1 * g.csplit;
-                        TO* de = C + m1 * g.rs1 + m2 * g.rs2 + ne1 * g.cs1 + ne2 * g.cs2;
-                        acc_t v = sv[e];
-                        if (beta != acc_t(0)) v += beta * (acc_t)(*de);
-                        *de = to_out<TO, acc_t>(v);
-                    }
+                    for (int e = 0; e < 8; ++e) e8[e] = k + e < g.K ? p[e] : bf16_t(0);
+                    v = __builtin_bit_cast(uint4, e8);
                 }
-            }
-            m += RSTEP;
-            m2 += RSTEP;
-            while (m2 >= g.rsplit) {
-                m2 -= g.rsplit;
-                ++m1;
+                *reinterpret_cast<uint4*>((o == 0 ? sa : sb) + (wave + NW * j) * 1024 + lane * 16) =
+                    v;
             }
         }
+    };
+
+    accv acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = accv{};
+
+    // one k-tile: two steps of k = 32; lane (li, lg) takes chunk 2 lg + s of
+    // its rows (rows li mod 8 = li & 7 in every 16-row block)
+    auto compute = [&](const char* sa, const char* sb) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int u = ((2 * lg + s) ^ (li & 7)) * 16;
+            uint4 fa[TM], fb[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+                fa[i] = *reinterpret_cast<const uint4*>(sa + (wm * WM + i * 16 + li) * ROWB + u);
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+                fb[j] = *reinterpret_cast<const uint4*>(sb + (wn * WN + j * 16 + li) * ROWB + u);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf8v, fa[i]), __builtin_bit_cast(bf8v, fb[j]),
+                        acc[i][j], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+
+    // full k-tiles: the stages alternate statically (two k-tiles per trip),
+    // so every LDS access names its array
+    const long long nfull = g.K / BK;
+    if (nfull > 0) {
+        dma(la0, lb0, 0);
+        __syncthreads();
+        for (long long kt = 0;;) {
+            if (kt + 1 < nfull) dma(la1, lb1, (kt + 1) * BK);
+            compute(la0, lb0);
+            __syncthreads();
+            if (++kt == nfull) break;
+            if (kt + 1 < nfull) dma(la0, lb0, (kt + 1) * BK);
+            compute(la1, lb1);
+            __syncthreads();
+            if (++kt == nfull) break;
+        }
     }
+    // the ragged last k-tile (every stage is free after the barrier above)
+    if (nfull * BK < g.K) {
+        tail(la0, lb0, nfull * BK);
+        __syncthreads();
+        compute(la0, lb0);
+    }
+
+    // epilogue: waves 2w and 2w+1 stage their blocks in array w
+    char* base = wave < 2 ? la0 : wave < 4 ? la1 : wave < 6 ? lb0 : lb1;
+    float* stage = reinterpret_cast<float*>(base + (wave & 1) * STAGE);
+    store_tile<bf16_t, TO, WM, WN, NPASS>(acc, stage, C, g, m0 + wm * WM, n0 + wn * WN, lane,
+                                          alpha, beta);
 }
 
 static bool aligned16(const void* p) {
@@ -488,9 +686,27 @@ static void launch_tiles(hipStream_t st, bool ta, bool tb, const TI* A, const TI
     }
 }
 
+// Launch of the LDS-DMA BF16 tile (configuration 8) over the batch.
+template <typename TO, int KIND>
+static void launch_lds_tiles(hipStream_t st, const bf16_t* A, const bf16_t* B, TO* C,
+                             const GemmShape& g, long long batch, float alpha, float beta) {
+    const long long ntm = (g.M + 255) / 256, ntn = (g.N + 255) / 256;
+    ADC_REQUIRE(ntm * ntn * 512 < (1LL << 32), "gemm: grid too large");
+    for (long long z0 = 0; z0 < batch; z0 += 65535) {
+        const long long nz = std::min<long long>(65535, batch - z0);
+        GemmShape gz = g;
+        gz.z0 = z0;
+        hipLaunchKernelGGL((k_gemm_lds<TO, KIND>), dim3((unsigned)(ntm * ntn), 1, (unsigned)nz),
+                           dim3(512), 0, st, A, B, C, gz, alpha, beta);
+        ADC_HIP(hipGetLastError());
+    }
+}
+
 // Tile configurations: (BM, BN, waves in M, waves in N).
 //   0: 64x64 (4x1)    1: 128x128 (2x2)   2: 128x128 (4x2)   3: 128x64 (2x2)
 //   4: 256x128 (2x2)  5: 256x256 (2x2)   6: 256x128 (4x2)   7: 256x256 (4x2)
+//   8: 256x256 (4x2), BF16 NT with operands loaded straight into LDS
+//      (k_gemm_lds; other products given 8 run as 7)
 // The 8-wave 256x256 tile gives each wave a 64x128 block: half the LDS reads
 // per multiply of the 64x64 blocks, which is what limits BF16. For FP64
 // the 4-wave 64x64 tile (four workgroups per CU) beats larger tiles on
@@ -505,7 +721,7 @@ template <> inline bool cfg_available<double>(int cfg) {
 }
 template <> inline bool cfg_available<float>(int cfg) { return cfg == 0 || cfg == 1 || cfg == 2; }
 template <> inline bool cfg_available<bf16_t>(int cfg) {
-    return cfg == 0 || cfg == 1 || cfg == 6 || cfg == 7;
+    return cfg == 0 || cfg == 1 || cfg == 6 || cfg == 7 || cfg == 8;
 }
 
 // untuned choice: the large tile when both sides fill it and the grid gives
@@ -592,6 +808,21 @@ void mfma_gemm(hipStream_t st, bool ta, bool tb, long long M, long long N, long 
             default: ADC_CFG(0, 64, 64, 4, 1)
         }
     } else {
+        // configuration 8 needs BF16 storage, the NT form and 16-byte aligned rows
+        if (cfg == 8) {
+            if constexpr (std::is_same<TI, bf16_t>::value) {
+                if (!ta && tb && g.vecA && g.vecB) {
+                    if (kind == 1)
+                        launch_lds_tiles<TO, 1>(st, A, B, C, g, batch, alpha, beta);
+                    else if (kind == 2)
+                        launch_lds_tiles<TO, 2>(st, A, B, C, g, batch, alpha, beta);
+                    else
+                        launch_lds_tiles<TO, 0>(st, A, B, C, g, batch, alpha, beta);
+                    return;
+                }
+            }
+            cfg = 7;
+        }
         switch (cfg) {
             ADC_CFG(1, 128, 128, 2, 2)
             ADC_CFG(6, 256, 128, 4, 2)

@@ -55,7 +55,10 @@ def _dev(a, dtype):
     return t.cuda()
 
 
-SHAPES = [(517, 389, 301), (300, 700, 1029), (64, 65, 7)]
+# K = 1000 and 40: rows of 16-byte aligned BF16 (K a multiple of 8), where the
+# NT form of configuration 8 loads its operands straight into LDS; 1000 ends in
+# a ragged k-tile, 40 has no full one
+SHAPES = [(517, 389, 301), (300, 700, 1029), (64, 65, 7), (517, 389, 1000), (300, 260, 40)]
 
 
 @pytest.mark.parametrize("dtype", [0, 1, 2, 3])
