@@ -139,9 +139,8 @@ void gemm_run(Engine& E, bool ta, bool tb, long long M, long long N, long long K
     }
     int ids[8];
     const int n = gemm_candidates<T>(ids);
-    float best = 3.0e38f;
-    int bc = ids[0];
-    for (int k = 0; k < n; ++k) {
+    float ms_of[8];
+    auto trial = [&](int k) {
         ADC_HIP(hipEventRecord(E.tev[0], E.stream));
         mfma_gemm<TI, T, TO>(E.stream, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, bt, Ct, ot,
                              batch, kind, ids[k], it2);
@@ -149,17 +148,33 @@ void gemm_run(Engine& E, bool ta, bool tb, long long M, long long N, long long K
         ADC_HIP(hipEventSynchronize(E.tev[1]));
         float ms = 0.f;
         ADC_HIP(hipEventElapsedTime(&ms, E.tev[0], E.tev[1]));
-        if (ms < best) {
-            best = ms;
-            bc = ids[k];
-        }
+        return ms;
+    };
+    for (int k = 0; k < n; ++k) ms_of[k] = trial(k);
+    // a close second (within 10 %) is timed again together with the leader,
+    // runner-up first, and each keeps its faster time: one launch of a few
+    // milliseconds is too noisy (clock changes between launches) to separate them
+    int b1 = 0, b2 = -1;
+    for (int k = 1; k < n; ++k)
+        if (ms_of[k] < ms_of[b1]) b1 = k;
+    for (int k = 0; k < n; ++k)
+        if (k != b1 && (b2 < 0 || ms_of[k] < ms_of[b2])) b2 = k;
+    if (b2 >= 0 && ms_of[b2] < 1.10f * ms_of[b1]) {
+        ms_of[b2] = std::min(ms_of[b2], trial(b2));
+        ms_of[b1] = std::min(ms_of[b1], trial(b1));
+        if (ms_of[b2] < ms_of[b1]) b1 = b2;
     }
+    const int bc = ids[b1];
+    const float best = ms_of[b1];
     E.tuned[key] = bc;
-    if (E.tune_log)
+    if (E.tune_log) {
         fprintf(stderr, "gemm tune: in %d B cmp %d B out %d B %c%c M %lld N %lld K %lld batch %lld "
-                "kind %d -> config %d (%.3f ms, %.1f TFLOP/s)\n",
+                "kind %d -> config %d (%.3f ms, %.1f TFLOP/s); candidates",
                 (int)sizeof(TI), (int)sizeof(T), (int)sizeof(TO), ta ? 'T' : 'N', tb ? 'T' : 'N',
                 M, N, K, batch * inner.n, kind, bc, best, flops / (best * 1e-3) / 1e12);
+        for (int k = 0; k < n; ++k) fprintf(stderr, " %d: %.3f ms", ids[k], ms_of[k]);
+        fprintf(stderr, "\n");
+    }
     if (Ct != C)
         mfma_gemm<TI, T, TO>(E.stream, ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,
                              out, batch, kind, bc, inner);
