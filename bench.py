@@ -47,7 +47,7 @@ PEAKS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 # the solver; FP32 products, used by the solver as a middle phase (BF16 ->
 # FP32 -> FP64)
 LEVEL = {"fp64": 0, "mixed": 1, "mixed3": 2}
-PP_TRAFFIC = {}
+PP_TRAFFIC = {("ea-adc3-o60v968", "mixed"): 8.8114e+12}
 HBM_GBPS = 8000.0
 
 
