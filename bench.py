@@ -445,7 +445,7 @@ def main():
                 "frac": (achieved / PEAKS_TFLOPS[dtype_key]) if achieved else None,
                 "traffic": PP_TRAFFIC.get((wl.name, precision)),
                 "kernel": "particle-particle term: (ac|bd) slab rebuild + contraction "
-                          "(k_gemm kinds 1 and 2)",
+                          "(k_gemm and k_gemm_lds, kinds 1 and 2)",
                 "ms_per_launch": ms_pp, "flops_per_launch": f_pp}
 
     dav = None
