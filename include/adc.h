@@ -400,7 +400,10 @@ void adc_batch_destroy(adc_batch* batch);
  * (a split of 0 means no split: m rs2, n cs2); the caller guarantees every
  * such offset lies inside C and that distinct (m, n) map to distinct offsets.
  * config: a tile configuration id from adc_gemm_configs, or -1 for the
- * library's own choice.  Synchronises the stream before returning.
+ * library's own choice.  Configuration 8 (the BF16 256x256 tile whose operands
+ * are loaded straight into LDS) applies to BF16 storage (dtype 3) in the NT
+ * form (ta = 0, tb = 1) with 16-byte aligned rows; other products given 8 run
+ * as 7.  Synchronises the stream before returning.
  * Errors: ADC_E_ARG (bad dtype, sizes, leading dimensions, map or config),
  * ADC_E_HIP.  adc_gemm_configs writes the configuration ids compiled for a
  * dtype into ids (at most 8) and returns their count (ADC_E_ARG for a bad
