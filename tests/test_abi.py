@@ -71,3 +71,35 @@ def test_host_validation_without_gpu():
     assert lib.adc_batch_set_option(None, b"tol_e", 1e-8) == adc.ADC_E_ARG
     assert lib.adc_batch_context(None, 0) is None
     lib.adc_batch_destroy(None)
+
+
+def test_gemm_configs_and_argument_checks_without_gpu():
+    """The tile configurations each product type offers (a static list), and
+    adc_gemm's argument checks, which run before any device work."""
+    import paper_2012_06714_amd as adc
+    lib = adc.lib
+    ids = (ctypes.c_int * 8)()
+    assert lib.adc_gemm_configs(4, ids) == adc.ADC_E_ARG
+    assert lib.adc_gemm_configs(0, None) == adc.ADC_E_ARG
+    got = {}
+    for dtype in range(4):
+        n = lib.adc_gemm_configs(dtype, ids)
+        assert 1 <= n <= 8
+        got[dtype] = [ids[k] for k in range(n)]
+    assert got[0] == [0, 2, 3] and got[1] == [0, 1, 2]
+    # BF16 products: the LDS-DMA tile (8) beside the register-staged ones
+    assert got[2] == got[3] == [0, 1, 6, 7, 8]
+    dummy = ctypes.c_void_p(256)
+    g = lib.adc_gemm
+    ll = ctypes.c_longlong
+    args = lambda **kw: dict(dict(dtype=3, ta=0, tb=1, M=ll(4), N=ll(4), K=ll(8), alpha=1.0,
+                                  A=dummy, lda=ll(8), B=dummy, ldb=ll(8), beta=0.0, C=dummy,
+                                  ldc=ll(4), map=None, config=-1, stream=None), **kw)
+    call = lambda **kw: g(*args(**kw).values())
+    assert call(config=9) == adc.ADC_E_ARG and "config" in adc.last_error()
+    assert call(config=-2) == adc.ADC_E_ARG
+    assert call(dtype=4) == adc.ADC_E_ARG
+    assert call(M=ll(0)) == adc.ADC_E_ARG
+    assert call(A=None) == adc.ADC_E_ARG
+    assert call(lda=ll(7)) == adc.ADC_E_ARG and "leading" in adc.last_error()
+    assert call(ldc=ll(3)) == adc.ADC_E_ARG
